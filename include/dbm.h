@@ -1,0 +1,168 @@
+/*
+ * dbm.h -- C ABI of libdbm: the per-time-step update of the multi-component
+ * D2V16 discrete Boltzmann model (Lin, Luo, Fei and Succi, "A multi-component
+ * discrete Boltzmann model for nonequilibrium reactive flows",
+ * arXiv:2006.15932) on AMD Instinct MI355X (gfx950).
+ *
+ * One step advances every species' 16 discrete distributions f_i^s on a 2-D
+ * grid (Eq.3): NND upwind convection, per-cell moments, f^eq = M^{-1} fhat
+ * (Eq.16) with M inverted once on the host in FP64, BGK collision (Eq.4) plus
+ * reaction (Eq.5) and force (Eq.6) sources, and the Runge-Kutta stage combine
+ * (forward Euler, the paper's scheme, or third-order TVD Runge-Kutta).
+ *
+ * Conventions shared by every entry point
+ *  - Return value: DBM_OK (0) or a negative DBM_ERR_* code; nothing throws or
+ *    aborts across the ABI.  dbm_last_error() gives a thread-local message.
+ *  - Host arrays are owned by the caller, always FP64, row-major with x
+ *    fastest: species fields [S][ny][nx], scalar fields [ny][nx], the
+ *    distribution [S][16][ny][nx].  Conversion to the storage precision
+ *    happens inside the library.
+ *  - Device memory: the caller allocates one workspace of
+ *    dbm_workspace_bytes() bytes (for example a torch uint8 tensor on the
+ *    GPU) and keeps it alive until dbm_destroy().  The library allocates no
+ *    device memory of its own; the handle owns only host tables, HIP events
+ *    and the captured HIP graphs.
+ *  - Streams: all device work is ordered on the hip_stream given to
+ *    dbm_create (NULL = the legacy default stream).  dbm_step is
+ *    asynchronous; every entry point that returns data to the host
+ *    synchronises the stream first.  Kernel failures surface at the next
+ *    synchronising call as DBM_ERR_HIP.
+ *  - Velocity ordering of the 16 planes of one species (Eq.15): group a
+ *    (i=0..3) = v_a*{(1,0),(0,1),(-1,0),(0,-1)}, group b (4..7) =
+ *    v_b*{(1,1),(-1,1),(-1,-1),(1,-1)}, group c (8..11) like a with v_c,
+ *    group d (12..15) like b with v_d; eta_g is shared within group g.
+ */
+#ifndef DBM_H
+#define DBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DBM_OK = 0,
+  DBM_ERR_ARG = -1,          /* invalid argument or configuration            */
+  DBM_ERR_SINGULAR_M = -2,   /* moment matrix rank < 16 or cond_1 > 1e12     */
+  DBM_ERR_HIP = -3,          /* HIP runtime failure (message kept)           */
+  DBM_ERR_NONFINITE = -4,    /* NaN/Inf or negative density found by check   */
+  DBM_ERR_UNSUPPORTED = -5,  /* valid but not supported (see each call)      */
+  DBM_ERR_WORKSPACE = -6     /* workspace missing, misaligned or too small   */
+};
+
+enum { DBM_FP64 = 0, DBM_FP32_BULK = 1 };        /* storage / bulk arithmetic */
+enum { DBM_EULER = 0, DBM_TVD_RK3 = 1 };         /* time scheme               */
+enum { DBM_LIM_MINMOD = 0, DBM_LIM_NONE = 1 };   /* NND limiter or unlimited  */
+enum { DBM_BC_PERIODIC = 0, DBM_BC_OUTFLOW = 1, DBM_BC_WALL = 2 };
+enum { DBM_FORCE_T_EXACT = 0, DBM_FORCE_T_SAME = 1 };
+
+/* One species (Eq.7 and Eq.15): molar mass m, extra degrees of freedom I,
+ * relaxation time tau (Eq.4), stoichiometric coefficient a (Eq.1, negative
+ * for reactants), speeds v[g] and internal-energy parameters eta[g] of the
+ * four velocity groups g = a, b, c, d. */
+typedef struct {
+  double m, I, tau, a_stoich;
+  double v[4];
+  double eta[4];
+} dbm_species;
+
+/* One-step overall reaction of Eqs.(1)-(2): rate omega = k_ov n^F n^O
+ * exp(-Ea_over_R / T); extent xi = omega*tau within the relaxation time;
+ * Q = heat released per unit extent.  k_ov == 0 disables the source. */
+typedef struct {
+  int fuel, oxidiser;
+  double k_ov, Ea_over_R, Q;
+} dbm_reaction;
+
+/* One simulation instance. */
+typedef struct {
+  int nx, ny;                    /* grid size, >= 1                           */
+  double dx, dy, dt;             /* spacings and time step, > 0               */
+  int bc_x, bc_y;                /* DBM_BC_*; walls are specular              */
+  int nspecies;                  /* 1 .. 16                                   */
+  const dbm_species *species;    /* nspecies entries                          */
+  const dbm_reaction *reaction;  /* NULL = no chemistry                       */
+  double accel[2];               /* external acceleration a (Eq.6)            */
+  int precision;                 /* DBM_FP64 | DBM_FP32_BULK                  */
+  int time_scheme;               /* DBM_EULER | DBM_TVD_RK3                   */
+  int limiter;                   /* DBM_LIM_MINMOD | DBM_LIM_NONE             */
+  int force_T_mode;              /* temperature T_dagger of Eq.(6)            */
+} dbm_config;
+
+typedef struct dbm_s *dbm_handle;
+
+/* Bytes of device workspace needed by ninst instances (0 on invalid input).
+ * Pure host computation; no GPU needed. */
+size_t dbm_workspace_bytes(const dbm_config *cfgs, int ninst);
+
+/* Validate the configurations, build per-species tables (velocity set of
+ * Eq.15, moment matrix rows listed after Eq.14 with row 9 = (v^2+eta^2) v_y,
+ * its FP64 inverse and the symmetry blocks derived from it), upload them into
+ * dev_workspace and return a handle.  ninst > 1 makes a batched handle: every
+ * instance must share nspecies, precision, time_scheme and limiter; each
+ * dbm_step advances all of them with one launch per stage.
+ * Errors: DBM_ERR_ARG (bad sizes, indices, non-positive m, tau, dt, dx, dy,
+ * negative I), DBM_ERR_SINGULAR_M, DBM_ERR_UNSUPPORTED (reaction with unequal
+ * tau across species, or mixed template parameters in a batch),
+ * DBM_ERR_WORKSPACE (NULL, unaligned to 256 bytes, or ws_bytes too small),
+ * DBM_ERR_HIP. */
+int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_workspace,
+               size_t ws_bytes, dbm_handle *out);
+
+/* Release host resources (graphs, events).  The workspace stays the caller's. */
+int dbm_destroy(dbm_handle h);
+
+/* f := f^eq(n^s, u, T) in every cell of instance inst (Eq.16).
+ * n_sp [S][ny][nx] molar concentrations, ux, uy, T [ny][nx]. */
+int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
+                   const double *uy, const double *T);
+
+/* Write / read the raw distribution [S][16][ny][nx] (FP64 host arrays),
+ * rounded to / widened from the storage precision. */
+int dbm_set_f(dbm_handle h, int inst, const double *f);
+int dbm_get_f(dbm_handle h, int inst, double *f);
+
+/* Advance every instance by nsteps time steps.  Asynchronous on the stream
+ * unless the non-finite check is enabled (then DBM_ERR_NONFINITE may be
+ * returned after a synchronisation). */
+int dbm_step(dbm_handle h, int nsteps);
+
+/* Macroscopic fields of instance inst: rho^s = m^s n^s [S][ny][nx] and the
+ * mixture ux, uy, T [ny][nx] (any pointer may be NULL).  Synchronises. */
+int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, double *T);
+
+/* Nonequilibrium measures of Eqs.(17)-(20), taken against f^eq(n^s, u, T):
+ * delta [S][12][ny][nx] in the order Delta_2 xx, xy, yy; Delta_3,1 x, y;
+ * Delta_3 xxx, xxy, xyy, yyy; Delta_4,2 xx, xy, yy (may be NULL), and FP64
+ * domain totals [S+3] = mass^s, momentum x, y, energy (times dx dy), reduced
+ * in a fixed order (may be NULL).  Synchronises. */
+int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals);
+
+/* Options (dbm_set_option / dbm_get_option). */
+enum {
+  DBM_OPT_PATH = 1,         /* 0 fused one-pass kernels (default), 1 plain    */
+  DBM_OPT_GRAPH = 2,        /* 1 replay captured HIP graphs (default), 0 eager */
+  DBM_OPT_TILE_ROWS = 3,    /* rows marched per wavefront; 0 = autotune        */
+  DBM_OPT_CHECK_EVERY = 4,  /* non-finite check every K steps; 0 = off         */
+  DBM_OPT_BATCH_MODE = 5,   /* 0 one launch per stage for all instances,
+                               1 one launch per instance (comparison mode)     */
+  DBM_OPT_GRAPH_CHUNK = 6,  /* steps captured per graph (default 16)          */
+  DBM_OPT_PERSISTENT = 7    /* read only: resident wavefronts of a launch      */
+};
+int dbm_set_option(dbm_handle h, int option, int value);
+int dbm_get_option(dbm_handle h, int option, int *value);
+
+/* Time the dominant kernel (one stage of the fused or plain path) with HIP
+ * events recorded on the handle's stream around each of reps eager launches
+ * that write only a spare buffer; returns the mean duration in milliseconds.
+ * The simulation state is not changed.  Synchronises. */
+int dbm_time_stage_kernel(dbm_handle h, int reps, double *ms_per_launch);
+
+/* Thread-local description of the last error. */
+const char *dbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

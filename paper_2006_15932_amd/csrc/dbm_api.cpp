@@ -1,0 +1,739 @@
+// dbm_api.cpp -- C ABI of libdbm: validation, workspace layout, tile tables,
+// the autotuner, HIP graph capture and replay, and the host sides of the
+// diagnostics.  See include/dbm.h for the contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/dbm.h"
+#include "dbm_internal.hpp"
+
+namespace dbm {
+int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
+hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, const InstDev *insts,
+                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
+                        int out_idx, double alpha, double beta, hipStream_t st);
+hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, int *waves_per_cu);
+hipError_t launch_plain(bool fp32, const InstDev *insts, int inst, size_t cells, int S,
+                        int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
+                        hipStream_t st);
+hipError_t launch_init(bool fp32, const InstDev *insts, int inst, size_t cells,
+                       const double *fields, int out_idx, hipStream_t st);
+hipError_t launch_moments(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+                          double *dst, hipStream_t st);
+hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+                        int which, double *dst, hipStream_t st);
+int totals_blocks();
+hipError_t launch_totals(bool fp32, const InstDev *insts, int inst, int in_idx, int nq,
+                         double area, double *partials, double *out, hipStream_t st);
+hipError_t launch_widen(bool fp32, const void *src, double *dst, size_t n, hipStream_t st);
+hipError_t launch_narrow(bool fp32, const double *src, void *dst, size_t n, hipStream_t st);
+hipError_t launch_check(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+                        int *flag, hipStream_t st);
+hipError_t launch_dpp_probe(int *out, hipStream_t st);
+hipError_t launch_delay(double microseconds, hipStream_t st);
+}  // namespace dbm
+
+using namespace dbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(DBM_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+constexpr int kTilesPerRowStride = 60;  // output columns per wavefront tile
+
+int tiles_x(int nx) { return (nx + kTilesPerRowStride - 1) / kTilesPerRowStride; }
+
+struct Layout {
+  size_t sp_off = 0, inst_off = 0, tile_off = 0, part_off = 0, tot_off = 0, flag_off = 0,
+         probe_off = 0;
+  size_t tile_cap = 0;
+  std::vector<size_t> buf_off[3], scratch_off;
+  size_t total = 0;
+};
+
+int validate(const dbm_config *cfgs, int ninst) {
+  if (!cfgs || ninst < 1) return fail(DBM_ERR_ARG, "need at least one configuration");
+  for (int k = 0; k < ninst; ++k) {
+    const dbm_config &c = cfgs[k];
+    const std::string who = "instance " + std::to_string(k) + ": ";
+    if (c.nx < 1 || c.ny < 1) return fail(DBM_ERR_ARG, who + "nx, ny must be >= 1");
+    if ((double)c.nx * (double)c.ny > (double)(1 << 30))
+      return fail(DBM_ERR_ARG, who + "nx*ny above 2^30 cells");
+    if (!(c.dx > 0) || !(c.dy > 0) || !(c.dt > 0) || !std::isfinite(c.dx) ||
+        !std::isfinite(c.dy) || !std::isfinite(c.dt))
+      return fail(DBM_ERR_ARG, who + "dx, dy, dt must be positive and finite");
+    if (c.bc_x < 0 || c.bc_x > 2 || c.bc_y < 0 || c.bc_y > 2)
+      return fail(DBM_ERR_ARG, who + "unknown boundary condition");
+    if (c.nspecies < 1 || c.nspecies > kMaxSpecies || !c.species)
+      return fail(DBM_ERR_ARG, who + "nspecies must be 1..16 with a species array");
+    if (c.precision < 0 || c.precision > 1 || c.time_scheme < 0 || c.time_scheme > 1 ||
+        c.limiter < 0 || c.limiter > 1 || c.force_T_mode < 0 || c.force_T_mode > 1)
+      return fail(DBM_ERR_ARG, who + "unknown precision, scheme, limiter or force mode");
+    if (!std::isfinite(c.accel[0]) || !std::isfinite(c.accel[1]))
+      return fail(DBM_ERR_ARG, who + "non-finite acceleration");
+    for (int s = 0; s < c.nspecies; ++s) {
+      const dbm_species &sp = c.species[s];
+      if (!(sp.m > 0) || !(sp.tau > 0) || !(sp.I >= 0) || !std::isfinite(sp.m) ||
+          !std::isfinite(sp.tau) || !std::isfinite(sp.I))
+        return fail(DBM_ERR_ARG, who + "species needs m > 0, tau > 0, I >= 0");
+    }
+    if (c.reaction) {
+      const dbm_reaction &r = *c.reaction;
+      if (r.fuel < 0 || r.fuel >= c.nspecies || r.oxidiser < 0 || r.oxidiser >= c.nspecies ||
+          r.fuel == r.oxidiser)
+        return fail(DBM_ERR_ARG, who + "bad fuel/oxidiser indices");
+      if (!(r.k_ov >= 0) || !std::isfinite(r.k_ov) || !std::isfinite(r.Ea_over_R) ||
+          !std::isfinite(r.Q))
+        return fail(DBM_ERR_ARG, who + "bad reaction constants");
+      if (r.k_ov > 0)
+        for (int s = 1; s < c.nspecies; ++s)
+          if (c.species[s].tau != c.species[0].tau)
+            return fail(DBM_ERR_UNSUPPORTED,
+                        who + "a reaction needs one relaxation time for all species");
+    }
+    if (k > 0) {
+      const dbm_config &c0 = cfgs[0];
+      if (c.nspecies != c0.nspecies || c.precision != c0.precision ||
+          c.time_scheme != c0.time_scheme || c.limiter != c0.limiter)
+        return fail(DBM_ERR_UNSUPPORTED,
+                    who + "batched instances must share nspecies, precision, scheme, limiter");
+    }
+  }
+  return DBM_OK;
+}
+
+size_t esize(const dbm_config &c) { return c.precision == DBM_FP32_BULK ? 4 : 8; }
+
+void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
+  const int S = cfgs[0].nspecies;
+  size_t off = 0;
+  L.sp_off = off;
+  off = align_up(off + sizeof(SpeciesDev) * (size_t)ninst * S);
+  L.inst_off = off;
+  off = align_up(off + sizeof(InstDev) * (size_t)ninst);
+  L.tile_cap = 0;
+  for (int k = 0; k < ninst; ++k) L.tile_cap += (size_t)tiles_x(cfgs[k].nx) * cfgs[k].ny;
+  L.tile_off = off;
+  off = align_up(off + sizeof(Tile) * L.tile_cap);
+  L.part_off = off;
+  off = align_up(off + sizeof(double) * (size_t)totals_blocks() * (S + 3));
+  L.tot_off = off;
+  off = align_up(off + sizeof(double) * (S + 3));
+  L.flag_off = off;
+  off = align_up(off + sizeof(int));
+  L.probe_off = off;
+  off = align_up(off + sizeof(int) * 256);
+  for (int b = 0; b < 3; ++b) L.buf_off[b].resize(ninst);
+  L.scratch_off.resize(ninst);
+  for (int k = 0; k < ninst; ++k) {
+    const size_t cells = (size_t)cfgs[k].nx * cfgs[k].ny;
+    const size_t fbytes = (size_t)S * kNV * cells * esize(cfgs[k]);
+    for (int b = 0; b < 3; ++b) {
+      L.buf_off[b][k] = off;
+      off = align_up(off + fbytes);
+    }
+    size_t per_cell = std::max<size_t>((size_t)S * kNV * esize(cfgs[k]), 12 * sizeof(double));
+    per_cell = std::max<size_t>(per_cell, (size_t)(S + 3) * sizeof(double));
+    L.scratch_off[k] = off;
+    off = align_up(off + per_cell * cells);
+  }
+  L.total = off;
+}
+
+struct TuneKey {
+  int fp32, S, lim, scheme, bucket, ninst;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(fp32, S, lim, scheme, bucket, ninst) <
+           std::tie(o.fp32, o.S, o.lim, o.scheme, o.bucket, o.ninst);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+std::mutex g_probe_mu;
+int g_probe_state = 0;  // 0 unknown, 1 ok, -1 failed
+
+}  // namespace
+
+struct dbm_s {
+  int ninst = 0, S = 0, scheme = 0, lim = 0;
+  bool fp32 = false;
+  std::vector<dbm_config> cfg;
+  std::vector<std::vector<dbm_species>> species;
+  std::vector<dbm_reaction> reaction;
+  hipStream_t stream = nullptr, cap = nullptr;
+  char *ws = nullptr;
+  Layout L;
+  std::vector<InstDev> inst;
+  int cur = 0;
+  int path = 0, use_graph = 1, tile_rows_opt = 0, check_every = 0, batch_mode = 0,
+      graph_chunk = 16;
+  bool fused_ok = false;
+  int rows = 0;  // rows per tile in use (0 = not tuned yet)
+  std::vector<Tile> tiles;
+  std::vector<int> tile_begin;
+  int resident = 0;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  long long since_check = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  const InstDev *d_inst() const { return (const InstDev *)(ws + L.inst_off); }
+  const Tile *d_tiles() const { return (const Tile *)(ws + L.tile_off); }
+  size_t cells(int k) const { return (size_t)cfg[k].nx * cfg[k].ny; }
+};
+
+namespace {
+
+void clear_graphs(dbm_handle h) {
+  for (auto &kv : h->graphs) hipGraphExecDestroy(kv.second);
+  h->graphs.clear();
+}
+
+bool use_fused(dbm_handle h) { return h->path == 0 && h->fused_ok; }
+
+void build_tiles(dbm_handle h, int rows) {
+  h->tiles.clear();
+  h->tile_begin.assign(h->ninst + 1, 0);
+  for (int k = 0; k < h->ninst; ++k) {
+    h->tile_begin[k] = (int)h->tiles.size();
+    const int nx = h->cfg[k].nx, ny = h->cfg[k].ny;
+    const int r = std::max(1, std::min(rows, ny));
+    for (int y0 = 0; y0 < ny; y0 += r)
+      for (int tx = 0; tx < tiles_x(nx); ++tx)
+        h->tiles.push_back(Tile{k, tx * kTilesPerRowStride, y0, std::min(r, ny - y0)});
+  }
+  h->tile_begin[h->ninst] = (int)h->tiles.size();
+}
+
+int upload_tiles(dbm_handle h) {
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.tile_off, h->tiles.data(), sizeof(Tile) * h->tiles.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+// One stage: out = alpha f^n + beta (f + dt L(f)), on stream st.
+int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alpha, double beta,
+                  bool rkc, hipStream_t st) {
+  if (use_fused(h)) {
+    if (h->batch_mode == 0) {
+      const int nt = (int)h->tiles.size();
+      const int grid = std::max(1, std::min(nt, h->resident));
+      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->d_inst(), h->d_tiles(), nt, grid,
+                          in_idx, fn_idx, out_idx, alpha, beta, st));
+    } else {
+      for (int k = 0; k < h->ninst; ++k) {
+        const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
+        const int grid = std::max(1, std::min(nt, h->resident));
+        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->d_inst(), h->d_tiles() + b, nt, grid,
+                            in_idx, fn_idx, out_idx, alpha, beta, st));
+      }
+    }
+  } else {
+    for (int k = 0; k < h->ninst; ++k)
+      HIPCHK(launch_plain(h->fp32, h->d_inst(), k, h->cells(k), h->S, in_idx, fn_idx, out_idx,
+                          alpha, beta, rkc, st));
+  }
+  return DBM_OK;
+}
+
+// Enqueue one full time step starting from state buffer `parity`.
+int enqueue_step(dbm_handle h, int &parity, hipStream_t st) {
+  int rc;
+  if (h->scheme == DBM_EULER) {
+    rc = enqueue_stage(h, parity, parity, 1 - parity, 0.0, 1.0, false, st);
+    if (rc) return rc;
+    parity = 1 - parity;
+  } else {  // Shu-Osher TVD-RK3; stage 3 overwrites f^n in place (centre reads only)
+    if ((rc = enqueue_stage(h, 0, 0, 1, 0.0, 1.0, false, st))) return rc;
+    if ((rc = enqueue_stage(h, 1, 0, 2, 0.75, 0.25, true, st))) return rc;
+    if ((rc = enqueue_stage(h, 2, 0, 0, 1.0 / 3.0, 2.0 / 3.0, true, st))) return rc;
+    parity = 0;
+  }
+  return DBM_OK;
+}
+
+// The stage launch a step is made of (Euler) or that dominates it (RK3,
+// stages 2-3), writing only a spare buffer.
+int enqueue_timed_stage(dbm_handle h, hipStream_t st) {
+  if (h->scheme == DBM_EULER) return enqueue_stage(h, h->cur, h->cur, 1 - h->cur, 0.0, 1.0, false, st);
+  return enqueue_stage(h, 1, 0, 2, 0.75, 0.25, true, st);
+}
+
+int time_stage(dbm_handle h, int reps, double *ms) {
+  // Fill the queue behind a short delay kernel so that back-to-back launches
+  // are timed, not the host's submission rate.
+  HIPCHK(launch_delay(50.0 + 25.0 * reps, h->stream));
+  std::vector<hipEvent_t> ev(2 * reps);
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  int rc = DBM_OK;
+  for (int r = 0; r < reps && !rc; ++r) {
+    HIPCHK(hipEventRecord(ev[2 * r], h->stream));
+    rc = enqueue_timed_stage(h, h->stream);
+    HIPCHK(hipEventRecord(ev[2 * r + 1], h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double tot = 0.0;
+  for (int r = 0; r < reps && !rc; ++r) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]));
+    tot += t;
+  }
+  for (auto &e : ev) hipEventDestroy(e);
+  if (rc) return rc;
+  *ms = tot / reps;
+  return DBM_OK;
+}
+
+int ensure_tuned(dbm_handle h) {
+  if (!use_fused(h)) return DBM_OK;
+  int want = h->tile_rows_opt;
+  int maxny = 1;
+  size_t tot = 0;
+  for (int k = 0; k < h->ninst; ++k) {
+    maxny = std::max(maxny, h->cfg[k].ny);
+    tot += h->cells(k);
+  }
+  const TuneKey key{h->fp32 ? 1 : 0, h->S, h->lim, h->scheme,
+                    (int)std::lround(std::log2((double)tot + 1.0)), h->ninst};
+  if (want <= 0) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) want = it->second;
+  }
+  if (want <= 0) {
+    if (h->scheme == DBM_TVD_RK3) {  // give the timed stage realistic inputs
+      for (int k = 0; k < h->ninst; ++k)
+        HIPCHK(hipMemcpyAsync(h->inst[k].buf[1], h->inst[k].buf[0],
+                              (size_t)h->S * kNV * h->cells(k) * (h->fp32 ? 4 : 8),
+                              hipMemcpyDeviceToDevice, h->stream));
+    }
+    const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
+    double best = 1e300;
+    int best_rows = 1;
+    for (int r : cands) {
+      if (r > 2 * maxny && r > 1) break;
+      build_tiles(h, r);
+      int rc = upload_tiles(h);
+      if (rc) return rc;
+      double ms = 0.0;
+      if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
+      if ((rc = time_stage(h, 3, &ms))) return rc;
+      if (ms < best) {
+        best = ms;
+        best_rows = r;
+      }
+    }
+    want = best_rows;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = want;
+  }
+  if (want != h->rows || h->tiles.empty()) {
+    build_tiles(h, want);
+    int rc = upload_tiles(h);
+    if (rc) return rc;
+    h->rows = want;
+    clear_graphs(h);
+  }
+  return DBM_OK;
+}
+
+int get_graph(dbm_handle h, int parity, int nsteps, hipGraphExec_t *out) {
+  auto key = std::make_pair(parity, nsteps);
+  auto it = h->graphs.find(key);
+  if (it != h->graphs.end()) {
+    *out = it->second;
+    return DBM_OK;
+  }
+  HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed));
+  int p = parity, rc = DBM_OK;
+  for (int s = 0; s < nsteps && !rc; ++s) rc = enqueue_step(h, p, h->cap);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap, &g);
+  if (rc) {
+    if (g) hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(DBM_ERR_HIP, std::string("capture: ") + hipGetErrorString(e));
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (e != hipSuccess)
+    return fail(DBM_ERR_HIP, std::string("instantiate: ") + hipGetErrorString(e));
+  h->graphs[key] = ex;
+  *out = ex;
+  return DBM_OK;
+}
+
+int check_state(dbm_handle h) {
+  int *flag = (int *)(h->ws + h->L.flag_off);
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
+  for (int k = 0; k < h->ninst; ++k)
+    HIPCHK(launch_check(h->fp32, h->d_inst(), k, h->cells(k), h->cur, flag, h->stream));
+  int hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  if (hflag) return fail(DBM_ERR_NONFINITE, "non-finite value or negative density in f");
+  return DBM_OK;
+}
+
+int run_probe(dbm_handle h) {
+  std::lock_guard<std::mutex> g(g_probe_mu);
+  if (g_probe_state != 0) return DBM_OK;
+  int *d = (int *)(h->ws + h->L.probe_off);
+  int out[256];
+  HIPCHK(launch_dpp_probe(d, h->stream));
+  HIPCHK(hipMemcpyAsync(out, d, sizeof(out), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  bool ok = true;
+  for (int rep = 0; rep < 2; ++rep)
+    for (int l = 0; l < 64; ++l) {
+      const int shr = out[128 * rep + l], shl = out[128 * rep + 64 + l];
+      ok &= shr == (l == 0 ? -1 : l - 1);
+      ok &= shl == (l == 63 ? -1 : l + 1);
+    }
+  g_probe_state = ok ? 1 : -1;
+  return DBM_OK;
+}
+
+int check_inst(dbm_handle h, int inst) {
+  if (!h) return fail(DBM_ERR_ARG, "null handle");
+  if (inst < 0 || inst >= h->ninst) return fail(DBM_ERR_ARG, "instance index out of range");
+  return DBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dbm_last_error(void) { return g_err.c_str(); }
+
+size_t dbm_workspace_bytes(const dbm_config *cfgs, int ninst) {
+  if (validate(cfgs, ninst) != DBM_OK) return 0;
+  Layout L;
+  compute_layout(cfgs, ninst, L);
+  return L.total;
+}
+
+int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_workspace,
+               size_t ws_bytes, dbm_handle *out) {
+  if (!out) return fail(DBM_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate(cfgs, ninst);
+  if (rc) return rc;
+  Layout L;
+  compute_layout(cfgs, ninst, L);
+  std::vector<SpeciesDev> tabs((size_t)ninst * cfgs[0].nspecies);
+  for (int k = 0; k < ninst; ++k)
+    for (int s = 0; s < cfgs[k].nspecies; ++s) {
+      std::string err;
+      rc = build_species(cfgs[k].species[s], cfgs[k], tabs[(size_t)k * cfgs[0].nspecies + s], err);
+      if (rc)
+        return fail(rc, "instance " + std::to_string(k) + " species " + std::to_string(s) +
+                            ": " + err);
+    }
+  if (!dev_workspace || ((uintptr_t)dev_workspace % kAlign) != 0)
+    return fail(DBM_ERR_WORKSPACE, "workspace is NULL or not 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(DBM_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
+                                       " bytes");
+  dbm_s *h = new dbm_s();
+  h->ninst = ninst;
+  h->S = cfgs[0].nspecies;
+  h->fp32 = cfgs[0].precision == DBM_FP32_BULK;
+  h->scheme = cfgs[0].time_scheme;
+  h->lim = cfgs[0].limiter;
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char *)dev_workspace;
+  h->L = L;
+  h->cfg.assign(cfgs, cfgs + ninst);
+  h->species.resize(ninst);
+  h->reaction.resize(ninst);
+  h->fused_ok = h->S <= kMaxFusedSpecies;
+  for (int k = 0; k < ninst; ++k) {
+    h->species[k].assign(cfgs[k].species, cfgs[k].species + cfgs[k].nspecies);
+    h->cfg[k].species = h->species[k].data();
+    if (cfgs[k].reaction) {
+      h->reaction[k] = *cfgs[k].reaction;
+      h->cfg[k].reaction = &h->reaction[k];
+    } else {
+      h->cfg[k].reaction = nullptr;
+    }
+    if (cfgs[k].bc_x == DBM_BC_WALL) h->fused_ok = false;
+    InstDev d;
+    std::memset(&d, 0, sizeof(d));
+    for (int b = 0; b < 3; ++b) d.buf[b] = h->ws + L.buf_off[b][k];
+    d.scratch = h->ws + L.scratch_off[k];
+    d.sp = (const SpeciesDev *)(h->ws + L.sp_off) + (size_t)k * h->S;
+    d.nx = cfgs[k].nx;
+    d.ny = cfgs[k].ny;
+    d.bcx = cfgs[k].bc_x;
+    d.bcy = cfgs[k].bc_y;
+    d.S = h->S;
+    const dbm_reaction *r = cfgs[k].reaction;
+    d.react = (r && r->k_ov > 0) ? 1 : 0;
+    d.fuel = r ? r->fuel : 0;
+    d.oxid = r ? r->oxidiser : 1;
+    d.k_ov = r ? r->k_ov : 0.0;
+    d.EaR = r ? r->Ea_over_R : 0.0;
+    d.Q2 = r ? 2.0 * r->Q : 0.0;
+    d.force = (cfgs[k].accel[0] != 0.0 || cfgs[k].accel[1] != 0.0) ? 1 : 0;
+    d.fmode = cfgs[k].force_T_mode;
+    d.ax = cfgs[k].accel[0];
+    d.ay = cfgs[k].accel[1];
+    d.dt = cfgs[k].dt;
+    d.dx = cfgs[k].dx;
+    d.dy = cfgs[k].dy;
+    d.lim = cfgs[k].limiter;
+    h->inst.push_back(d);
+  }
+  auto bail = [&](int code) {
+    if (h->cap) hipStreamDestroy(h->cap);
+    if (h->ev0) hipEventDestroy(h->ev0);
+    if (h->ev1) hipEventDestroy(h->ev1);
+    delete h;
+    return code;
+  };
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking)) != hipSuccess ||
+      (e = hipEventCreate(&h->ev0)) != hipSuccess || (e = hipEventCreate(&h->ev1)) != hipSuccess)
+    return bail(fail(DBM_ERR_HIP, std::string("stream/event creation: ") + hipGetErrorString(e)));
+  if ((e = hipMemcpyAsync(h->ws + L.sp_off, tabs.data(), sizeof(SpeciesDev) * tabs.size(),
+                          hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (e = hipMemcpyAsync(h->ws + L.inst_off, h->inst.data(), sizeof(InstDev) * ninst,
+                          hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    return bail(fail(DBM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e)));
+  if ((rc = run_probe(h))) return bail(rc);
+  if (g_probe_state < 0) h->fused_ok = false;
+  if (h->fused_ok) {
+    int per_cu = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if ((e = fused_occupancy(h->fp32, h->S, h->lim, h->scheme == DBM_TVD_RK3, &per_cu)) !=
+            hipSuccess ||
+        (e = hipGetDevice(&dev)) != hipSuccess ||
+        (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
+      return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
+    h->resident = std::max(kNumXcd, per_cu * prop.multiProcessorCount);
+    h->resident = (h->resident / kNumXcd) * kNumXcd;
+  }
+  *out = h;
+  return DBM_OK;
+}
+
+int dbm_destroy(dbm_handle h) {
+  if (!h) return fail(DBM_ERR_ARG, "null handle");
+  hipStreamSynchronize(h->stream);
+  clear_graphs(h);
+  if (h->cap) hipStreamDestroy(h->cap);
+  if (h->ev0) hipEventDestroy(h->ev0);
+  if (h->ev1) hipEventDestroy(h->ev1);
+  delete h;
+  return DBM_OK;
+}
+
+int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
+                   const double *uy, const double *T) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!n_sp || !ux || !uy || !T) return fail(DBM_ERR_ARG, "NULL field array");
+  const size_t cells = h->cells(inst), S = h->S;
+  double *stage = (double *)h->inst[inst].scratch;
+  HIPCHK(hipMemcpyAsync(stage, n_sp, sizeof(double) * S * cells, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(stage + S * cells, ux, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(stage + (S + 1) * cells, uy, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(stage + (S + 2) * cells, T, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(launch_init(h->fp32, h->d_inst(), inst, cells, stage, h->cur, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_set_f(dbm_handle h, int inst, const double *f) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!f) return fail(DBM_ERR_ARG, "NULL f");
+  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
+  void *dst = h->inst[inst].buf[h->cur];
+  if (!h->fp32) {
+    HIPCHK(hipMemcpyAsync(dst, f, sizeof(double) * nplanes * cells, hipMemcpyHostToDevice, h->stream));
+  } else {
+    double *stage = (double *)h->inst[inst].scratch;
+    for (size_t p = 0; p < nplanes; ++p) {
+      HIPCHK(hipMemcpyAsync(stage, f + p * cells, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
+      HIPCHK(launch_narrow(true, stage, (float *)dst + p * cells, cells, h->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_get_f(dbm_handle h, int inst, double *f) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!f) return fail(DBM_ERR_ARG, "NULL f");
+  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
+  const void *src = h->inst[inst].buf[h->cur];
+  if (!h->fp32) {
+    HIPCHK(hipMemcpyAsync(f, src, sizeof(double) * nplanes * cells, hipMemcpyDeviceToHost, h->stream));
+  } else {
+    double *stage = (double *)h->inst[inst].scratch;
+    for (size_t p = 0; p < nplanes; ++p) {
+      HIPCHK(launch_widen(true, (const float *)src + p * cells, stage, cells, h->stream));
+      HIPCHK(hipMemcpyAsync(f + p * cells, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_step(dbm_handle h, int nsteps) {
+  if (!h) return fail(DBM_ERR_ARG, "null handle");
+  if (nsteps < 0) return fail(DBM_ERR_ARG, "nsteps < 0");
+  int rc = ensure_tuned(h);
+  if (rc) return rc;
+  while (nsteps > 0) {
+    int n = nsteps;
+    if (h->check_every > 0) n = (int)std::min<long long>(n, h->check_every - h->since_check);
+    if (h->use_graph) {
+      int left = n;
+      while (left > 0) {
+        const int chunk = std::min(left, std::max(1, h->graph_chunk));
+        hipGraphExec_t ex;
+        if ((rc = get_graph(h, h->cur, chunk, &ex))) return rc;
+        HIPCHK(hipGraphLaunch(ex, h->stream));
+        if (h->scheme == DBM_EULER && (chunk & 1)) h->cur = 1 - h->cur;
+        left -= chunk;
+      }
+    } else {
+      for (int s = 0; s < n; ++s)
+        if ((rc = enqueue_step(h, h->cur, h->stream))) return rc;
+    }
+    nsteps -= n;
+    if (h->check_every > 0) {
+      h->since_check += n;
+      if (h->since_check >= h->check_every) {
+        h->since_check = 0;
+        if ((rc = check_state(h))) return rc;
+      }
+    }
+  }
+  return DBM_OK;
+}
+
+int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, double *T) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  const size_t cells = h->cells(inst), S = h->S;
+  double *stage = (double *)h->inst[inst].scratch;
+  HIPCHK(launch_moments(h->fp32, h->d_inst(), inst, cells, h->cur, stage, h->stream));
+  if (rho_sp) HIPCHK(hipMemcpyAsync(rho_sp, stage, sizeof(double) * S * cells, hipMemcpyDeviceToHost, h->stream));
+  if (ux) HIPCHK(hipMemcpyAsync(ux, stage + S * cells, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
+  if (uy) HIPCHK(hipMemcpyAsync(uy, stage + (S + 1) * cells, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
+  if (T) HIPCHK(hipMemcpyAsync(T, stage + (S + 2) * cells, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  const size_t cells = h->cells(inst);
+  double *stage = (double *)h->inst[inst].scratch;
+  if (delta) {
+    for (int s = 0; s < h->S; ++s) {
+      HIPCHK(launch_noneq(h->fp32, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
+      HIPCHK(hipMemcpyAsync(delta + (size_t)s * 12 * cells, stage, sizeof(double) * 12 * cells,
+                            hipMemcpyDeviceToHost, h->stream));
+    }
+  }
+  if (totals) {
+    const int nq = h->S + 3;
+    double *part = (double *)(h->ws + h->L.part_off), *tot = (double *)(h->ws + h->L.tot_off);
+    HIPCHK(launch_totals(h->fp32, h->d_inst(), inst, h->cur, nq,
+                         h->cfg[inst].dx * h->cfg[inst].dy, part, tot, h->stream));
+    HIPCHK(hipMemcpyAsync(totals, tot, sizeof(double) * nq, hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_set_option(dbm_handle h, int option, int value) {
+  if (!h) return fail(DBM_ERR_ARG, "null handle");
+  switch (option) {
+    case DBM_OPT_PATH:
+      if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "path must be 0 or 1");
+      if (value == 0 && !h->fused_ok)
+        return fail(DBM_ERR_UNSUPPORTED, "fused path needs S <= 4, no x walls, DPP check ok");
+      h->path = value;
+      break;
+    case DBM_OPT_GRAPH: h->use_graph = value ? 1 : 0; break;
+    case DBM_OPT_TILE_ROWS:
+      if (value < 0 || value > 4096) return fail(DBM_ERR_ARG, "tile rows out of range");
+      h->tile_rows_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
+    case DBM_OPT_CHECK_EVERY:
+      if (value < 0) return fail(DBM_ERR_ARG, "check interval < 0");
+      h->check_every = value;
+      h->since_check = 0;
+      break;
+    case DBM_OPT_BATCH_MODE:
+      if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "batch mode must be 0 or 1");
+      h->batch_mode = value;
+      break;
+    case DBM_OPT_GRAPH_CHUNK:
+      if (value < 1 || value > 4096) return fail(DBM_ERR_ARG, "graph chunk out of range");
+      h->graph_chunk = value;
+      break;
+    default: return fail(DBM_ERR_ARG, "unknown or read-only option");
+  }
+  clear_graphs(h);
+  return DBM_OK;
+}
+
+int dbm_get_option(dbm_handle h, int option, int *value) {
+  if (!h || !value) return fail(DBM_ERR_ARG, "null handle or value");
+  switch (option) {
+    case DBM_OPT_PATH: *value = use_fused(h) ? 0 : 1; break;
+    case DBM_OPT_GRAPH: *value = h->use_graph; break;
+    case DBM_OPT_TILE_ROWS: *value = h->rows; break;
+    case DBM_OPT_CHECK_EVERY: *value = h->check_every; break;
+    case DBM_OPT_BATCH_MODE: *value = h->batch_mode; break;
+    case DBM_OPT_GRAPH_CHUNK: *value = h->graph_chunk; break;
+    case DBM_OPT_PERSISTENT: *value = h->resident; break;
+    default: return fail(DBM_ERR_ARG, "unknown option");
+  }
+  return DBM_OK;
+}
+
+int dbm_time_stage_kernel(dbm_handle h, int reps, double *ms_per_launch) {
+  if (!h || !ms_per_launch || reps < 1) return fail(DBM_ERR_ARG, "bad arguments");
+  int rc = ensure_tuned(h);
+  if (rc) return rc;
+  return time_stage(h, reps, ms_per_launch);
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// dbm_internal.hpp -- structures shared by the host runtime and the gfx950
+// kernels of libdbm.  Everything here lives in the caller's device workspace.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace dbm {
+
+constexpr int kNV = 16;        // discrete velocities per species (D2V16)
+constexpr int kMaxSpecies = 16;
+constexpr int kMaxFusedSpecies = 4;   // one-pass kernels are instantiated for S <= 4
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;     // MI355X: 8 accelerator complex dies, one L2 each
+
+enum Bc { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_WALL = 2 };
+
+// Per-species tables of one instance.
+//
+// The 16 planes form four orbits of four velocities under the symmetry group
+// of the square (Eq.15).  Within an orbit g the distribution is rewritten as
+//   A_g = sum of the four values, B_g = alternating sum, X_g, Y_g = first
+//   moments with the sign of v_x, v_y,
+// and the moment matrix M splits into independent blocks acting on
+//   (A_a, A_b, A_c, A_d)   rows 1, v^2+eta^2, v_x^2+v_y^2, (v^2+eta^2)(v_x^2+v_y^2)
+//   (B_a, B_c)             rows v_x^2-v_y^2, (v^2+eta^2)(v_x^2-v_y^2)
+//   (B_b, B_d)             rows v_x v_y, (v^2+eta^2) v_x v_y
+//   (X_a, X_b, X_c, X_d)   rows v_x, (v^2+eta^2) v_x, v_x^3, v_x v_y^2
+//   (Y_a, Y_b, Y_c, Y_d)   the same block with x and y exchanged.
+// KA, KB1, KB2, KE are the FP64 inverses of those blocks with the orbit
+// reconstruction factors (1/4 for A and B, 1/2 or 1/4 for X and Y) folded in.
+struct SpeciesDev {
+  // FP64 per-cell scalar chain
+  double m, K, tau, a, inv_m;
+  double vg[4];          // group speed parameter v_g
+  double qg[4];          // |v|^2 + eta^2 of group g
+  double omega;          // dt / tau
+  double cgx[4], cgy[4]; // dt v_g / dx, dt v_g / dy
+  double KA[16], KB1[4], KB2[4], KE[16];
+  double Minv[kNV * kNV];  // dense FP64 inverse (plain path, init, diagnostics)
+  double M[kNV * kNV];     // dense moment matrix (diagnostics)
+  // FP32 copies for the FP32-bulk kernels
+  float omega_f;
+  float cgx_f[4], cgy_f[4];
+  float KA_f[16], KB1_f[4], KB2_f[4], KE_f[16];
+  float vg_f[4], qg_f[4];
+  int mirx[kNV], miry[kNV];
+  int pad_[2];
+};
+
+struct InstDev {
+  void *buf[3];          // three f buffers [S][16][ny][nx] in storage precision
+  void *scratch;         // per-instance scratch (plain-path f^eq, staging)
+  const SpeciesDev *sp;  // S entries
+  int nx, ny, bcx, bcy;
+  int S;
+  int react, fuel, oxid;
+  double k_ov, EaR, Q2;  // Q2 = 2 Q
+  int force, fmode;
+  double ax, ay;
+  double dt, dx, dy;
+  int lim;
+  int pad_;
+};
+
+// One tile: a wavefront marches `rows` rows of 64 columns starting at (x0, y0).
+struct Tile {
+  int inst, x0, y0, rows;
+};
+
+}  // namespace dbm

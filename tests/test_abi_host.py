@@ -1,0 +1,115 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/dbm.h, and rejects invalid
+configurations before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_15932_amd import dbm as D
+from paper_2006_15932_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "dbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 12
+    L = D.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(D.SIGNATURES)
+
+
+def _cfg(p, **kw):
+    return D.Configs([p.with_(**kw)] if kw else [p])
+
+
+def test_workspace_bytes_is_positive_and_scales():
+    p = W.reacting(n=64, steps=1)
+    b64 = D.dbm_workspace_bytes(D.Configs([p], "fp64"))
+    b32 = D.dbm_workspace_bytes(D.Configs([p], "fp32"))
+    assert b64 > 0 and b32 > 0 and b32 < b64
+    # three f buffers at least
+    assert b32 >= 3 * 3 * 16 * 64 * 64 * 4
+    big = D.dbm_workspace_bytes(D.Configs([W.reacting(n=128, steps=1)], "fp32"))
+    assert 3.5 < big / b32 < 4.5
+
+
+@pytest.mark.parametrize("bad,code", [
+    (dict(nx=0), D.DBM_ERR_ARG),
+    (dict(ny=-3), D.DBM_ERR_ARG),
+    (dict(dt=0.0), D.DBM_ERR_ARG),
+    (dict(dx=float("nan")), D.DBM_ERR_ARG),
+    (dict(bc_x=7), D.DBM_ERR_ARG),
+    (dict(scheme=5), D.DBM_ERR_ARG),
+])
+def test_create_rejects_bad_grid(bad, code):
+    p = W.reacting(n=16, steps=1)
+    cfg = D.Configs([p.with_(**bad)])
+    assert D.dbm_workspace_bytes(cfg) == 0
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(cfg, 0, 0, 0)
+    assert e.value.code == code
+
+
+def test_create_rejects_bad_species_and_reaction():
+    p = W.reacting(n=16, steps=1)
+    sp = list(p.species)
+    sp[1] = W.Species(m=-2.0)
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(D.Configs([p.with_(species=sp)]), 0, 0, 0)
+    assert e.value.code == D.DBM_ERR_ARG
+    sp = [W.make_species(2.0, tau=1e-5, a=-2), W.make_species(32.0, tau=3e-5, a=-1),
+          W.make_species(18.0, a=2)]
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(D.Configs([p.with_(species=sp)]), 0, 0, 0)
+    assert e.value.code == D.DBM_ERR_UNSUPPORTED
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(D.Configs([p.with_(reaction=dict(fuel=0, oxid=0, k_ov=1.0, Ea_over_R=1.0))]),
+                     0, 0, 0)
+    assert e.value.code == D.DBM_ERR_ARG
+
+
+def test_create_rejects_singular_moment_matrix():
+    p = W.reacting(n=16, steps=1)
+    sp = [W.Species(m=1.0, eta=(0.5, 0.5, 0.5, 0.5))] * 3
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(D.Configs([p.with_(species=sp, reaction=None)]), 0, 0, 0)
+    assert e.value.code == D.DBM_ERR_SINGULAR_M
+    assert "singular" in D.last_error()
+
+
+def test_create_rejects_missing_or_small_workspace():
+    p = W.reacting(n=16, steps=1)
+    cfg = D.Configs([p])
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(cfg, 0, 0, 1 << 30)
+    assert e.value.code == D.DBM_ERR_WORKSPACE
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(cfg, 0, 4096, 16)
+    assert e.value.code == D.DBM_ERR_WORKSPACE
+
+
+def test_batch_must_share_template_parameters():
+    a = W.reacting(n=16, steps=1)
+    b = W.reacting(n=32, steps=1).with_(scheme=W.RK3)
+    cfg = D.Configs([a, b])
+    assert D.dbm_workspace_bytes(cfg) == 0
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_create(cfg, 0, 0, 0)
+    assert e.value.code == D.DBM_ERR_UNSUPPORTED
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = D.lib()
+    assert L.dbm_step(None, 1) == D.DBM_ERR_ARG
+    assert L.dbm_destroy(None) == D.DBM_ERR_ARG
+    assert L.dbm_moments(None, 0, None, None, None, None) == D.DBM_ERR_ARG

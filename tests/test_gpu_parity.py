@@ -1,0 +1,230 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle
+on the same seeded inputs.
+
+Bars: FP64 storage within 1e-10 normwise relative L-infinity on f and on
+rho, u, T; FP32-bulk within 1e-5 on rho, u, T.  Sizes span several 60-column
+tiles with ragged tails in x and y; every boundary type, both limiters, both
+time schemes, force modes, chemistry, the plain path and batched launches are
+covered.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import f_error, field_errors, gpu_run, oracle_run
+from oracle import oracle as O
+from paper_2006_15932_amd import dbm as D
+from paper_2006_15932_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+FP32_TOL = 1e-5
+
+
+def _check_fp64(p, steps, **kw):
+    print("case", p.name, p.nx, p.ny, "S=%d" % p.S, "steps=%d" % steps, kw, flush=True)
+    sim = gpu_run(p, steps, "fp64", **kw)
+    o, fo = oracle_run(p, steps)
+    fg = sim.get_f()
+    ef = f_error(fg, fo)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    assert ef < FP64_TOL, (ef, errs)
+    for k, v in errs.items():
+        assert v < FP64_TOL, (k, v, errs)
+    return sim
+
+
+def small_reacting(nx=130, ny=37, **kw):
+    return W.reacting(n=nx, ny=ny, steps=1, precision="fp64", **kw)
+
+
+def small_rt(nx=70, ny=44, **kw):
+    return W.rayleigh_taylor(n=nx, ny=ny, steps=1, precision="fp64", **kw)
+
+
+def small_shear(nx=90, ny=64, **kw):
+    return W.shear_layer(n=nx, ny=ny, steps=1, precision="fp64", **kw)
+
+
+def test_fused_path_is_active_and_dpp_layout_ok():
+    sim = D.Simulation(small_reacting(), precision="fp64")
+    assert sim.get_option(D.DBM_OPT_PATH) == 0
+    assert sim.get_option(D.DBM_OPT_PERSISTENT) >= 256
+
+
+def test_sod_fp64_euler():
+    _check_fp64(W.sod(steps=1000), 1000)
+
+
+def test_sod_fp64_rk3():
+    _check_fp64(W.sod(steps=300, scheme=W.RK3), 300)
+
+
+@pytest.mark.parametrize("scheme,lim", [(W.EULER, W.LIM_MINMOD), (W.RK3, W.LIM_NONE)])
+def test_reacting_fp64(scheme, lim):
+    _check_fp64(small_reacting().with_(scheme=scheme, limiter=lim), 40)
+
+
+@pytest.mark.parametrize("scheme,mode", [(W.EULER, W.FORCE_T_EXACT), (W.RK3, W.FORCE_T_SAME)])
+def test_rayleigh_taylor_walls_force_fp64(scheme, mode):
+    _check_fp64(small_rt().with_(scheme=scheme, force_T_mode=mode), 40)
+
+
+def test_shear_layer_four_species_fp64():
+    _check_fp64(small_shear(), 30)
+
+
+def test_outflow_both_axes_fp64():
+    p = small_reacting(nx=61, ny=33).with_(bc_x=W.OUTFLOW, bc_y=W.OUTFLOW)
+    _check_fp64(p, 30)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 9), (7, 1), (3, 2), (60, 5), (121, 3)])
+def test_degenerate_and_ragged_sizes_fp64(nx, ny):
+    _check_fp64(small_reacting(nx=nx, ny=ny), 12)
+
+
+def test_plain_path_fp64():
+    _check_fp64(small_rt(nx=33, ny=21).with_(scheme=W.RK3), 20, path=1)
+    _check_fp64(small_reacting(nx=47, ny=19), 20, path=1)
+
+
+def test_x_walls_use_plain_path_fp64():
+    p = small_rt(nx=26, ny=18).with_(bc_x=W.WALL)
+    sim = _check_fp64(p, 20)
+    assert sim.get_option(D.DBM_OPT_PATH) == 1
+
+
+def test_five_species_use_plain_path_fp64():
+    p = small_reacting(nx=20, ny=12)
+    sp = list(p.species) + [W.make_species(28.0), W.make_species(40.0)]
+    q = p.with_(species=sp, n_sp=np.concatenate([p.n_sp, 0.01 * p.n_sp[:2]]))
+    sim = _check_fp64(q, 10)
+    assert sim.get_option(D.DBM_OPT_PATH) == 1
+
+
+def test_tile_shape_does_not_change_fp64_bits():
+    p = small_reacting(nx=125, ny=41)
+    ref = None
+    for rows in (1, 3, 16, 64):
+        sim = gpu_run(p, 15, "fp64", tile_rows=rows)
+        assert sim.get_option(D.DBM_OPT_TILE_ROWS) == rows
+        f = sim.get_f()
+        if ref is None:
+            ref = f
+        else:
+            np.testing.assert_array_equal(f, ref)
+
+
+def test_graph_replay_equals_eager():
+    p = small_reacting(nx=64, ny=30)
+    a = gpu_run(p, 17, "fp32", options={D.DBM_OPT_GRAPH: 0})
+    b = gpu_run(p, 17, "fp32", options={D.DBM_OPT_GRAPH: 1, D.DBM_OPT_GRAPH_CHUNK: 4})
+    fa = a.get_f()
+    np.testing.assert_array_equal(fa, b.get_f())
+    b.step(8)                       # replays of cached graphs, then compare again
+    a.step(8)
+    np.testing.assert_array_equal(a.get_f(), b.get_f())
+
+
+def test_checkpoint_restart_is_bit_exact():
+    p = small_rt(nx=64, ny=40)
+    for prec in ("fp64", "fp32"):
+        a = gpu_run(p, 20, prec)
+        b = gpu_run(p, 10, prec)
+        f_mid = b.get_f()
+        c = D.Simulation(p, precision=prec)
+        c.set_f(f_mid)
+        c.step(10)
+        np.testing.assert_array_equal(a.get_f(), c.get_f())
+
+
+def test_fp32_bulk_reacting_within_1e5():
+    p = W.reacting(n=64, steps=500, precision="fp32")
+    sim = gpu_run(p, 500, "fp32")
+    o, fo = oracle_run(p, 500)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    print("fp32 reacting errors", errs, flush=True)
+    for k in ("rho", "u", "T"):
+        assert errs[k] < FP32_TOL, errs
+
+
+def test_fp32_bulk_rayleigh_taylor_within_1e5():
+    p = W.rayleigh_taylor(n=64, steps=500, precision="fp32")
+    sim = gpu_run(p, 500, "fp32")
+    o, fo = oracle_run(p, 500)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    print("fp32 RT errors", errs, flush=True)
+    for k in ("rho", "u", "T"):
+        assert errs[k] < FP32_TOL, errs
+
+
+def _batch(precision="fp64"):
+    sizes = [(37, 29), (64, 64), (100, 20), (16, 130), (61, 61)]
+    out = []
+    for k, (nx, ny) in enumerate(sizes):
+        p = W.reacting(n=nx, ny=ny, steps=1, seed=777 + k, tau=1e-5 * (1 + k),
+                       t_hot=2.0 + 0.4 * k, precision=precision)
+        out.append(p)
+    return out
+
+
+def test_batched_persistent_matches_oracle_and_sequential():
+    probs = _batch()
+    runs = {}
+    for mode in (0, 1):
+        sim = D.Simulation(probs, precision="fp64")
+        sim.set_option(D.DBM_OPT_BATCH_MODE, mode)
+        for k in range(len(probs)):
+            sim.set_fields(k)
+        sim.step(15)
+        runs[mode] = [sim.get_f(k) for k in range(len(probs))]
+    for k, p in enumerate(probs):
+        np.testing.assert_array_equal(runs[0][k], runs[1][k])
+        o, fo = oracle_run(p, 15)
+        assert f_error(runs[0][k], fo) < FP64_TOL
+
+
+def test_moments_and_noneq_match_oracle():
+    p = small_shear(nx=70, ny=50)
+    sim = gpu_run(p, 12, "fp64")
+    o, fo = oracle_run(p, 12)
+    rg, uxg, uyg, Tg = sim.moments()
+    ro, uxo, uyo, To = o.moments(fo)
+    for a, b in ((rg, ro), (uxg, uxo), (uyg, uyo), (Tg, To)):
+        assert np.abs(a - b).max() <= FP64_TOL * np.abs(b).max()
+    dg, tg = sim.noneq()
+    do, to = o.noneq(fo)
+    for s in range(p.S):
+        for k in range(12):
+            scale = np.abs(do[s, k]).max() + 1e-300
+            assert np.abs(dg[s, k] - do[s, k]).max() <= 1e-8 * scale, (s, k)
+    np.testing.assert_allclose(tg, to, rtol=1e-11, atol=1e-15 * np.abs(to).max())
+
+
+def test_zero_steps_and_restore_fields():
+    p = small_reacting(nx=40, ny=12)
+    sim = gpu_run(p, 0, "fp64")
+    o = O.Oracle(p)
+    f0 = o.init_equilibrium(*W.fields(p))
+    assert f_error(sim.get_f(), f0) < 1e-14
+
+
+def test_nonfinite_check_reports_error():
+    p = small_reacting(nx=32, ny=8)
+    sim = gpu_run(p, 0, "fp64", options={D.DBM_OPT_CHECK_EVERY: 2})
+    f = sim.get_f()
+    f[1, 3, 4, 5] = np.nan
+    sim.set_f(f)
+    with pytest.raises(D.DbmError) as e:
+        sim.step(2)
+    assert e.value.code == D.DBM_ERR_NONFINITE
+
+
+def test_stage_kernel_timer_leaves_state_unchanged():
+    p = small_reacting(nx=120, ny=40)
+    sim = gpu_run(p, 3, "fp32")
+    f = sim.get_f()
+    ms = sim.time_stage_kernel(5)
+    assert ms > 0
+    np.testing.assert_array_equal(f, sim.get_f())
