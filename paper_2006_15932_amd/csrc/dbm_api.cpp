@@ -482,6 +482,9 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
       h->cfg[k].reaction = nullptr;
     }
     if (cfgs[k].bc_x == DBM_BC_WALL) h->fused_ok = false;
+    // the one-pass kernel addresses one species' 16 planes with 32-bit offsets
+    if ((double)kNV * cfgs[k].nx * (double)cfgs[k].ny * (h->fp32 ? 4.0 : 8.0) >= 4294967296.0)
+      h->fused_ok = false;
     InstDev d;
     std::memset(&d, 0, sizeof(d));
     for (int b = 0; b < 3; ++b) d.buf[b] = h->ws + L.buf_off[b][k];

@@ -27,22 +27,27 @@ enum Bc { BC_PERIODIC = 0, BC_OUTFLOW = 1, BC_WALL = 2 };
 //   (B_b, B_d)             rows v_x v_y, (v^2+eta^2) v_x v_y
 //   (X_a, X_b, X_c, X_d)   rows v_x, (v^2+eta^2) v_x, v_x^3, v_x v_y^2
 //   (Y_a, Y_b, Y_c, Y_d)   the same block with x and y exchanged.
-// KA, KB1, KB2, KE are the FP64 inverses of those blocks with the orbit
-// reconstruction factors (1/4 for A and B, 1/2 or 1/4 for X and Y) folded in.
+// MA, MB1, MB2, ME are those blocks (row-major, unknowns in the order above);
+// KA, KB1, KB2, KE are their FP64 inverses with the orbit reconstruction
+// factors (1/4 for A and B, 1/2 or 1/4 for X and Y) folded in.
 struct SpeciesDev {
   // FP64 per-cell scalar chain
   double m, K, tau, a, inv_m;
+  double inv_neg_a;      // 1 / (-a) for reactants (a < 0), else 0
+  double inv_K;          // 1 / (D + I)
   double vg[4];          // group speed parameter v_g
   double qg[4];          // |v|^2 + eta^2 of group g
   double omega;          // dt / tau
   double cgx[4], cgy[4]; // dt v_g / dx, dt v_g / dy
   double KA[16], KB1[4], KB2[4], KE[16];
+  double MA[16], MB1[4], MB2[4], ME[16];  // the blocks themselves (moments of f)
   double Minv[kNV * kNV];  // dense FP64 inverse (plain path, init, diagnostics)
   double M[kNV * kNV];     // dense moment matrix (diagnostics)
   // FP32 copies for the FP32-bulk kernels
   float omega_f;
   float cgx_f[4], cgy_f[4];
   float KA_f[16], KB1_f[4], KB2_f[4], KE_f[16];
+  float MA_f[16], MB1_f[4], MB2_f[4], ME_f[16];
   float vg_f[4], qg_f[4];
   int mirx[kNV], miry[kNV];
   int pad_[2];

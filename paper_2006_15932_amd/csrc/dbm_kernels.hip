@@ -31,25 +31,59 @@ namespace dbm {
 // ---------------------------------------------------------------------------
 // Small device helpers
 // ---------------------------------------------------------------------------
+// Pointers into HBM read from the instance table are generic; casting them
+// to the global address space lets the compiler emit global (not flat)
+// memory instructions.
+template <typename T> using gptr = const T __attribute__((address_space(1))) *;
+template <typename T> using gptr_mut = T __attribute__((address_space(1))) *;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const void *p) {
+  return (gptr<T>)(p);
+}
+template <typename T> __device__ __forceinline__ gptr_mut<T> as_global_mut(void *p) {
+  return (gptr_mut<T>)(p);
+}
+
+// Species tables are read through the constant address space: wave-uniform,
+// read-only, so every access is a scalar load.
+#define DBM_CONST __attribute__((address_space(4)))
+using SpC = const SpeciesDev DBM_CONST;
+__device__ __forceinline__ SpC *as_const(const SpeciesDev *p) { return (SpC *)(p); }
+
 template <typename T> struct Tab;
 template <> struct Tab<float> {
-  static __device__ __forceinline__ const float *KA(const SpeciesDev &s) { return s.KA_f; }
-  static __device__ __forceinline__ const float *KB1(const SpeciesDev &s) { return s.KB1_f; }
-  static __device__ __forceinline__ const float *KB2(const SpeciesDev &s) { return s.KB2_f; }
-  static __device__ __forceinline__ const float *KE(const SpeciesDev &s) { return s.KE_f; }
-  static __device__ __forceinline__ float cgx(const SpeciesDev &s, int g) { return s.cgx_f[g]; }
-  static __device__ __forceinline__ float cgy(const SpeciesDev &s, int g) { return s.cgy_f[g]; }
-  static __device__ __forceinline__ float omega(const SpeciesDev &s) { return s.omega_f; }
+  static __device__ __forceinline__ const float DBM_CONST *KA(SpC &s) { return s.KA_f; }
+  static __device__ __forceinline__ const float DBM_CONST *KB1(SpC &s) { return s.KB1_f; }
+  static __device__ __forceinline__ const float DBM_CONST *KB2(SpC &s) { return s.KB2_f; }
+  static __device__ __forceinline__ const float DBM_CONST *KE(SpC &s) { return s.KE_f; }
+  static __device__ __forceinline__ const float DBM_CONST *MA(SpC &s) { return s.MA_f; }
+  static __device__ __forceinline__ const float DBM_CONST *MB1(SpC &s) { return s.MB1_f; }
+  static __device__ __forceinline__ const float DBM_CONST *MB2(SpC &s) { return s.MB2_f; }
+  static __device__ __forceinline__ const float DBM_CONST *ME(SpC &s) { return s.ME_f; }
+  static __device__ __forceinline__ float cgx(SpC &s, int g) { return s.cgx_f[g]; }
+  static __device__ __forceinline__ float cgy(SpC &s, int g) { return s.cgy_f[g]; }
+  static __device__ __forceinline__ float omega(SpC &s) { return s.omega_f; }
 };
 template <> struct Tab<double> {
-  static __device__ __forceinline__ const double *KA(const SpeciesDev &s) { return s.KA; }
-  static __device__ __forceinline__ const double *KB1(const SpeciesDev &s) { return s.KB1; }
-  static __device__ __forceinline__ const double *KB2(const SpeciesDev &s) { return s.KB2; }
-  static __device__ __forceinline__ const double *KE(const SpeciesDev &s) { return s.KE; }
-  static __device__ __forceinline__ double cgx(const SpeciesDev &s, int g) { return s.cgx[g]; }
-  static __device__ __forceinline__ double cgy(const SpeciesDev &s, int g) { return s.cgy[g]; }
-  static __device__ __forceinline__ double omega(const SpeciesDev &s) { return s.omega; }
+  static __device__ __forceinline__ const double DBM_CONST *KA(SpC &s) { return s.KA; }
+  static __device__ __forceinline__ const double DBM_CONST *KB1(SpC &s) { return s.KB1; }
+  static __device__ __forceinline__ const double DBM_CONST *KB2(SpC &s) { return s.KB2; }
+  static __device__ __forceinline__ const double DBM_CONST *KE(SpC &s) { return s.KE; }
+  static __device__ __forceinline__ const double DBM_CONST *MA(SpC &s) { return s.MA; }
+  static __device__ __forceinline__ const double DBM_CONST *MB1(SpC &s) { return s.MB1; }
+  static __device__ __forceinline__ const double DBM_CONST *MB2(SpC &s) { return s.MB2; }
+  static __device__ __forceinline__ const double DBM_CONST *ME(SpC &s) { return s.ME; }
+  static __device__ __forceinline__ double cgx(SpC &s, int g) { return s.cgx[g]; }
+  static __device__ __forceinline__ double cgy(SpC &s, int g) { return s.cgy[g]; }
+  static __device__ __forceinline__ double omega(SpC &s) { return s.omega; }
 };
+
+// Hide a wave-uniform pointer from loop-invariant code motion so that the
+// table values it points to are re-read from the scalar cache each row
+// instead of being held (and spilled) in scalar registers.
+template <typename P> __device__ __forceinline__ P launder(P p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
 
 // DPP whole-wavefront shifts: shr1 gives lane i the value of lane i-1,
 // shl1 the value of lane i+1; the lane with no source keeps `old`.
@@ -130,11 +164,11 @@ __device__ __forceinline__ int map_y(int r, int n, int bc, bool &flip) {
     return q < 0 ? q + n : q;
   }
   if (bc == BC_OUTFLOW) return r < 0 ? 0 : n - 1;
-  for (int it = 0; it < 64 && (r < 0 || r >= n); ++it) {
-    r = (r < 0) ? (-1 - r) : (2 * n - 1 - r);
-    flip = !flip;
-  }
-  return r < 0 ? 0 : (r >= n ? n - 1 : r);
+  // Reflections about the faces at 0 and n repeat with period 2n.
+  int q = r % (2 * n);
+  if (q < 0) q += 2 * n;
+  flip = q >= n;
+  return flip ? 2 * n - 1 - q : q;
 }
 
 // Block right-hand side of the equilibrium moments, in the order
@@ -167,9 +201,9 @@ __device__ __forceinline__ void eq_rhs(U n, U ux, U uy, U th, U K, U *r) {
 
 // f^eq of one species from its block right-hand side (plane order of Eq.15).
 template <typename T>
-__device__ __forceinline__ void block_feq(const SpeciesDev &sp, const T *r, T *f) {
-  const T *KA = Tab<T>::KA(sp), *KB1 = Tab<T>::KB1(sp), *KB2 = Tab<T>::KB2(sp),
-          *KE = Tab<T>::KE(sp);
+__device__ __forceinline__ void block_feq(SpC &sp, const T *r, T *f) {
+  const T DBM_CONST *KA = Tab<T>::KA(sp), *KB1 = Tab<T>::KB1(sp), *KB2 = Tab<T>::KB2(sp),
+                    *KE = Tab<T>::KE(sp);
   T al[4], xi[4], ps[4], be[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -201,7 +235,7 @@ __device__ __forceinline__ void block_feq(const SpeciesDev &sp, const T *r, T *f
 
 // FP64 raw moments n, j_x, j_y, E = sum f q of one species from its 16 values.
 template <typename T>
-__device__ __forceinline__ void species_moments(const SpeciesDev &sp, const T *c, double &n,
+__device__ __forceinline__ void species_moments(SpC &sp, const T *c, double &n,
                                                 double &jx, double &jy, double &E) {
   n = jx = jy = E = 0.0;
 #pragma unroll
@@ -222,13 +256,37 @@ __device__ __forceinline__ void species_moments(const SpeciesDev &sp, const T *c
   }
 }
 
-// Per-cell scalar chain in FP64: mixture u, T (conservation statement under
-// Eq.6), reaction (Eqs.1-2, 5) and the per-species right-hand side of the
-// combined equilibrium f^eq(n*,u,T*) + f^eq(n,u+,T+) - f^eq(n,u^s,T^s).
-template <typename T, int S>
-__device__ __forceinline__ void cell_rhs(const InstDev &I, const SpeciesDev *sp,
-                                         const double *n, const double *jx, const double *jy,
-                                         const double *E, T r[S][16]) {
+// Orbit components of one species' 16 values (plane order of Eq.15):
+// A = sum, B = alternating sum, X, Y = sums signed by v_x, v_y.
+template <typename T>
+__device__ __forceinline__ void orbit_parts(const T *c, T *A, T *B, T *X, T *Y) {
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const T c0 = c[4 * g], c1 = c[4 * g + 1], c2 = c[4 * g + 2], c3 = c[4 * g + 3];
+    const T s02 = c0 + c2, s13 = c1 + c3;
+    A[g] = s02 + s13;
+    B[g] = s02 - s13;
+    if ((g & 1) == 0) {
+      X[g] = c0 - c2; Y[g] = c1 - c3;
+    } else {
+      X[g] = (c0 + c3) - (c1 + c2); Y[g] = (c0 + c1) - (c2 + c3);
+    }
+  }
+}
+
+// Per-cell scalar chain in FP64: mixture u and T from the species moments
+// (the conservation statement under Eq.6 with Eqs.8-10), then the one-step
+// reaction of Eqs.(1)-(2) within tau (Eq.5): extent xi (n* = n + a xi) and
+// T* from the energy balance with heat Q per unit extent.
+struct CellState {
+  double ux, uy, Tst, xi;
+};
+
+template <int S>
+__device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp,
+                                           const double *n, const double *jx,
+                                           const double *jy, const double *E,
+                                           CellState &cs) {
   double rho = 0, px = 0, py = 0, e = 0, kn = 0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -238,12 +296,12 @@ __device__ __forceinline__ void cell_rhs(const InstDev &I, const SpeciesDev *sp,
     e = fma(sp[s].m, E[s], e);
     kn = fma(sp[s].K, n[s], kn);
   }
-  const double ux = px / rho, uy = py / rho;
-  const double Tm = (e - rho * (ux * ux + uy * uy)) / kn;
-  double nst[S];
-  double Tst = Tm;
-#pragma unroll
-  for (int s = 0; s < S; ++s) nst[s] = n[s];
+  const double irho = 1.0 / rho;
+  cs.ux = px * irho;
+  cs.uy = py * irho;
+  const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) / kn;
+  cs.Tst = Tm;
+  cs.xi = 0.0;
   if (I.react) {
     double nF = 0.0, nO = 0.0;
 #pragma unroll
@@ -254,33 +312,87 @@ __device__ __forceinline__ void cell_rhs(const InstDev &I, const SpeciesDev *sp,
     double xi = I.k_ov * nF * nO * exp(-I.EaR / Tm) * sp[0].tau;
 #pragma unroll
     for (int s = 0; s < S; ++s)
-      if (sp[s].a < 0.0) xi = fmin(xi, fmax(n[s], 0.0) / (-sp[s].a));
+      if (sp[s].a < 0.0) xi = fmin(xi, fmax(n[s], 0.0) * sp[s].inv_neg_a);
     double kns = 0.0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      nst[s] = fma(sp[s].a, xi, n[s]);
-      kns = fma(sp[s].K, nst[s], kns);
-    }
-    Tst = fma(Tm, kn, I.Q2 * xi) / kns;
+    for (int s = 0; s < S; ++s) kns = fma(sp[s].K, fma(sp[s].a, xi, n[s]), kns);
+    cs.Tst = fma(Tm, kn, I.Q2 * xi) / kns;
+    cs.xi = xi;
   }
+}
+
+// Collision + reaction + force of one species in moment space:
+//   df = f^eq(n*, u, T*) + [f^eq(n, u+, T+) - f^eq(n, u^s, T^s)] - f
+//      = M^{-1} (g - M f)
+// with g the combined equilibrium moments.  The rows of g - M f that carry
+// mass, momentum and energy are differenced in FP64 from the FP64 moments,
+// so the update conserves them to the rounding of the (small) difference
+// itself; the other rows are differenced in the storage precision.
+template <typename T>
+__device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp,
+                                                const T *c, double n, double jx, double jy,
+                                                double E, double ns, double ux, double uy,
+                                                double Tst, T *df) {
+  const double K = sp.K, th = Tst * sp.inv_m, u2 = ux * ux + uy * uy;
+  T r[16];
+  eq_rhs<T>((T)ns, (T)ux, (T)uy, (T)th, (T)K, r);
+  double d0 = ns - n, d1 = ns * fma(K, th, u2) - E, d8 = ns * ux - jx, d12 = ns * uy - jy;
+  const bool force = I.force && n > 1e-300;
+  double fd[16];
+  if (force) {
+    const double inv_n = 1.0 / n;
+    const double us = jx * inv_n, vs = jy * inv_n;
+    const double Ts = sp.m * (E * inv_n - us * us - vs * vs) / K;
+    double Td = Ts;
+    if (I.fmode == DBM_FORCE_T_EXACT)
+      Td = Ts - sp.m * sp.tau * sp.tau * (I.ax * I.ax + I.ay * I.ay) / K;
+    double r1[16], r2[16];
+    eq_rhs<double>(n, us + sp.tau * I.ax, vs + sp.tau * I.ay, Td * sp.inv_m, K, r1);
+    eq_rhs<double>(n, us, vs, Ts * sp.inv_m, K, r2);
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    eq_rhs<T>((T)nst[s], (T)ux, (T)uy, (T)(Tst * sp[s].inv_m), (T)sp[s].K, r[s]);
-    if (I.force && n[s] > 1e-300) {
-      const double inv_n = 1.0 / n[s];
-      const double us = jx[s] * inv_n, vs = jy[s] * inv_n;
-      const double Ts = sp[s].m * (E[s] * inv_n - us * us - vs * vs) / sp[s].K;
-      const double tau = sp[s].tau;
-      double Td = Ts;
-      if (I.fmode == DBM_FORCE_T_EXACT)
-        Td = Ts - sp[s].m * tau * tau * (I.ax * I.ax + I.ay * I.ay) / sp[s].K;
-      double r1[16], r2[16];
-      eq_rhs<double>(n[s], us + tau * I.ax, vs + tau * I.ay, Td * sp[s].inv_m, sp[s].K, r1);
-      eq_rhs<double>(n[s], us, vs, Ts * sp[s].inv_m, sp[s].K, r2);
-#pragma unroll
-      for (int k = 0; k < 16; ++k) r[s][k] += (T)(r1[k] - r2[k]);
-    }
+    for (int k = 0; k < 16; ++k) fd[k] = r1[k] - r2[k];
+    d0 += fd[0];
+    d1 += fd[1];
+    d8 += fd[8];
+    d12 += fd[12];
   }
+  T A[4], B[4], X[4], Y[4];
+  orbit_parts<T>(c, A, B, X, Y);
+  const T DBM_CONST *MA = Tab<T>::MA(sp), *MB1 = Tab<T>::MB1(sp), *MB2 = Tab<T>::MB2(sp),
+                    *ME = Tab<T>::ME(sp);
+  T d[16];
+  d[0] = (T)d0;
+  d[1] = (T)d1;
+  d[8] = (T)d8;
+  d[12] = (T)d12;
+#pragma unroll
+  for (int row = 2; row < 4; ++row) {
+    T m = MA[row * 4] * A[0];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) m = fma(MA[row * 4 + j], A[j], m);
+    d[row] = r[row] - m;
+  }
+  d[4] = r[4] - fma(MB1[1], B[2], MB1[0] * B[0]);
+  d[5] = r[5] - fma(MB1[3], B[2], MB1[2] * B[0]);
+  d[6] = r[6] - fma(MB2[1], B[3], MB2[0] * B[1]);
+  d[7] = r[7] - fma(MB2[3], B[3], MB2[2] * B[1]);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    T mx = ME[row * 4] * X[0], my = ME[row * 4] * Y[0];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      mx = fma(ME[row * 4 + j], X[j], mx);
+      my = fma(ME[row * 4 + j], Y[j], my);
+    }
+    d[8 + row] = r[8 + row] - mx;
+    d[12 + row] = r[12 + row] - my;
+  }
+  if (force) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k != 0 && k != 1 && k != 8 && k != 12) d[k] += (T)fd[k];
+  }
+  block_feq<T>(sp, d, df);
 }
 
 // Bijection of [0, n) that gives XCD x (wavefronts v with v % 8 == x) the
@@ -296,142 +408,192 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 // out = alpha * f^n + beta * (f + dt (C(f) + S(f)))   (RKC)
 // out = f + dt (C(f) + S(f))                          (!RKC)
 // ---------------------------------------------------------------------------
+// One wavefront's share of a tile: species `s`, 64 lanes = columns
+// x0-2 .. x0+61, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
+// exchange of per-cell FP64 moments, double-buffered by row parity.
 template <typename T, int S, int LIM, bool RKC>
-__device__ __forceinline__ void fused_tile(const InstDev &I, int x0, int y0, int rows,
-                                           int in_idx, int fn_idx, int out_idx, T alpha,
-                                           T beta) {
+__device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
+                                           int rows, int in_idx, int fn_idx, int out_idx,
+                                           T alpha, T beta, double (*mom)[4 * S][kWave]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
-  const SpeciesDev *sp = I.sp;
-  const T *__restrict__ fin = (const T *)I.buf[in_idx];
-  const T *__restrict__ fnb = (const T *)I.buf[fn_idx];
-  T *__restrict__ fout = (T *)I.buf[out_idx];
+  // One 64-bit base per species and buffer; everything below it is a 32-bit
+  // byte offset (the host keeps 16 planes of one species under 4 GiB).
   const size_t plane = (size_t)nx * (size_t)ny;
+  const uint32_t pl = (uint32_t)plane;
+  typedef const char __attribute__((address_space(1))) *gbytes;
+  typedef char __attribute__((address_space(1))) *gbytes_mut;
+  const gbytes fin = (gbytes)(as_global<T>(I.buf[in_idx]) + (size_t)s * kNV * plane);
+  const gbytes fnb = (gbytes)(as_global<T>(I.buf[fn_idx]) + (size_t)s * kNV * plane);
+  const gbytes_mut fout = (gbytes_mut)(as_global_mut<T>(I.buf[out_idx]) + (size_t)s * kNV * plane);
+  auto at = [&](gbytes b, uint32_t e) -> T {
+    return *(const T __attribute__((address_space(1))) *)(b + e * (uint32_t)sizeof(T));
+  };
   const int col = x0 - 2 + lane;                   // column held by this lane
   const int lcol = map_x(col, nx, I.bcx);          // where its value lives
   const bool writer = lane >= 2 && lane < kWave - 2 && col < nx;
+  const int yend = y0 + rows;
 
-  auto load = [&](int s, int i, int roff, bool flip) -> T {
-    const int p = flip ? mirror_y(i) : i;
-    return fin[(size_t)(s * kNV + p) * plane + (size_t)(roff + lcol)];
+  auto load = [&](int i, int roff, bool flip) -> T {
+    const uint32_t p = flip ? mirror_y(i) : i;
+    return at(fin, p * pl + (uint32_t)(roff + lcol));
   };
 
-  // State carried between rows.  For plane i of species s:
-  //   c  = f at the current row k (all planes)
+  // State carried between rows, per plane i:
+  //   c  = f at the current row k
   //   y1 = f_k - f_{k-1}           (v_y > 0)   or f_{k+1}   (v_y < 0)
   //   y2 = slope at row k-1        (v_y > 0)   or slope at row k (v_y < 0)
-  T c[S][kNV], y1[S][kNV], y2[S][kNV];
+  T c[kNV], y1[kNV], y2[kNV];
   {
     bool fm2, fm1, f0, fp1;
     const int rm2 = map_y(y0 - 2, ny, bcy, fm2) * nx, rm1 = map_y(y0 - 1, ny, bcy, fm1) * nx;
     const int r0 = map_y(y0, ny, bcy, f0) * nx, rp1 = map_y(y0 + 1, ny, bcy, fp1) * nx;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) {
-        const int sy = plane_sy(i);
-        if (sy > 0) {
-          const T a = load(s, i, rm2, fm2), b = load(s, i, rm1, fm1), cc = load(s, i, r0, f0);
-          c[s][i] = cc;
-          y1[s][i] = cc - b;
-          y2[s][i] = slope_pos<LIM>(b - a, cc - b);
-        } else if (sy < 0) {
-          const T a = load(s, i, rm1, fm1), cc = load(s, i, r0, f0), n1 = load(s, i, rp1, fp1);
-          c[s][i] = cc;
-          y1[s][i] = n1;
-          y2[s][i] = slope_neg<LIM>(cc - a, n1 - cc);
-        } else {
-          c[s][i] = load(s, i, r0, f0);
-          y1[s][i] = T(0);
-          y2[s][i] = T(0);
-        }
+    for (int i = 0; i < kNV; ++i) {
+      const int sy = plane_sy(i);
+      if (sy > 0) {
+        const T a = load(i, rm2, fm2), b = load(i, rm1, fm1), cc = load(i, r0, f0);
+        c[i] = cc;
+        y1[i] = cc - b;
+        y2[i] = slope_pos<LIM>(b - a, cc - b);
+      } else if (sy < 0) {
+        const T a = load(i, rm1, fm1), cc = load(i, r0, f0), n1 = load(i, rp1, fp1);
+        c[i] = cc;
+        y1[i] = n1;
+        y2[i] = slope_neg<LIM>(cc - a, n1 - cc);
+      } else {
+        c[i] = load(i, r0, f0);
+        y1[i] = T(0);
+        y2[i] = T(0);
       }
     }
   }
 
-  for (int k = y0; k < y0 + rows; ++k) {
-    bool fk1, fk2;
-    const int rk1 = map_y(k + 1, ny, bcy, fk1) * nx;
-    const int rk2 = map_y(k + 2, ny, bcy, fk2) * nx;
-    const int rk = k * nx;
+  // New values consumed by row k: row k+1 (v_y >= 0) or k+2 (v_y < 0).
+  auto issue = [&](int k, T *dst) {
+    bool fa, fb;
+    const int ra = map_y(k + 1, ny, bcy, fa) * nx, rb = map_y(k + 2, ny, bcy, fb) * nx;
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) dst[i] = plane_sy(i) < 0 ? load(i, rb, fb) : load(i, ra, fa);
+  };
 
-    // Moments and per-cell chain (FP64) from the centre values.
+  auto row = [&](int k, const T *cur, T *nxt) {
+    if (k + 1 < yend) issue(k + 1, nxt);             // two rows in flight
+    const int rk = k * nx;
+    SpC *sp = launder(as_const(I.sp));
+    SpC &me = sp[s];
+    T fnv[kNV];
+    if constexpr (RKC) {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) fnv[i] = at(fnb, (uint32_t)i * pl + (uint32_t)(rk + lcol));
+    }
+    // Own species' FP64 moments to LDS; one barrier; everyone's back.
+    double n0, jx0, jy0, E0;
+    species_moments<T>(me, c, n0, jx0, jy0, E0);
+    double(*mb)[kWave] = mom[k & 1];
+    mb[0 * S + s][lane] = n0;
+    mb[1 * S + s][lane] = jx0;
+    mb[2 * S + s][lane] = jy0;
+    mb[3 * S + s][lane] = E0;
+    __syncthreads();
     double n[S], jx[S], jy[S], E[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) species_moments<T>(sp[s], c[s], n[s], jx[s], jy[s], E[s]);
-    T r[S][16];
-    cell_rhs<T, S>(I, sp, n, jx, jy, E, r);
-
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      T feq[kNV];
-      block_feq<T>(sp[s], r[s], feq);
-      const T om = Tab<T>::omega(sp[s]);
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) {
-        const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
-        const T f = c[s][i];
-        T acc = f;
-        // x: NND difference from adjacent lanes.
-        if (sx != 0) {
-          const T fm1 = dpp_shr1(f, f), fp1 = dpp_shl1(f, f);
-          T Dx;
-          if (sx > 0) {
-            const T fm2 = dpp_shr1(fm1, fm1);
-            const T d0 = f - fm1, dp = fp1 - f, dm = fm1 - fm2;
-            Dx = d0 + T(0.5) * (slope_pos<LIM>(d0, dp) - slope_pos<LIM>(dm, d0));
-          } else {
-            const T fp2 = dpp_shl1(fp1, fp1);
-            const T dlo = fp1 - f, dhi = fp2 - fp1, dm = f - fm1;
-            Dx = dlo - T(0.5) * (slope_neg<LIM>(dlo, dhi) - slope_neg<LIM>(dm, dlo));
-          }
-          const T cx = Tab<T>::cgx(sp[s], g);
-          acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
-        }
-        // y: NND difference from the carried rows; advance the state.
-        if (sy > 0) {
-          const T fnew = load(s, i, rk1, fk1);
-          const T dn = fnew - f;
-          const T sk = slope_pos<LIM>(y1[s][i], dn);
-          const T Dy = y1[s][i] + T(0.5) * (sk - y2[s][i]);
-          acc = fma(-Tab<T>::cgy(sp[s], g), Dy, acc);
-          c[s][i] = fnew;
-          y1[s][i] = dn;
-          y2[s][i] = sk;
-        } else if (sy < 0) {
-          const T fnew = load(s, i, rk2, fk2);
-          const T n1 = y1[s][i];
-          const T dlo = n1 - f, dhi = fnew - n1;
-          const T tk1 = slope_neg<LIM>(dlo, dhi);
-          const T Dy = dlo - T(0.5) * (tk1 - y2[s][i]);
-          acc = fma(Tab<T>::cgy(sp[s], g), Dy, acc);
-          c[s][i] = n1;
-          y1[s][i] = fnew;
-          y2[s][i] = tk1;
-        } else {
-          c[s][i] = load(s, i, rk1, fk1);
-        }
-        T res = fma(om, feq[i] - f, acc);
-        const size_t o = (size_t)(s * kNV + i) * plane + (size_t)(rk + col);
-        if constexpr (RKC) {
-          const T fnv = fnb[(size_t)(s * kNV + i) * plane + (size_t)(rk + lcol)];
-          res = fma(alpha, fnv, beta * res);
-        }
-        if (writer) fout[o] = res;
-      }
+    for (int j = 0; j < S; ++j) {
+      n[j] = mb[0 * S + j][lane];
+      jx[j] = mb[1 * S + j][lane];
+      jy[j] = mb[2 * S + j][lane];
+      E[j] = mb[3 * S + j][lane];
     }
+    CellState cs;
+    cell_chain<S>(I, sp, n, jx, jy, E, cs);
+    T df[kNV];
+    collision_delta<T>(I, me, c, n0, jx0, jy0, E0, fma(me.a, cs.xi, n0), cs.ux, cs.uy, cs.Tst,
+                       df);
+    const T om = Tab<T>::omega(me);
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) {
+      const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
+      const T f = c[i];
+      T acc = f;
+      // x: NND difference from adjacent lanes.
+      if (sx != 0) {
+        const T fm1 = dpp_shr1(f, f), fp1 = dpp_shl1(f, f);
+        T Dx;
+        if (sx > 0) {
+          const T fm2 = dpp_shr1(fm1, fm1);
+          const T d0 = f - fm1, dp = fp1 - f, dm = fm1 - fm2;
+          Dx = d0 + T(0.5) * (slope_pos<LIM>(d0, dp) - slope_pos<LIM>(dm, d0));
+        } else {
+          const T fp2 = dpp_shl1(fp1, fp1);
+          const T dlo = fp1 - f, dhi = fp2 - fp1, dm = f - fm1;
+          Dx = dlo - T(0.5) * (slope_neg<LIM>(dlo, dhi) - slope_neg<LIM>(dm, dlo));
+        }
+        const T cx = Tab<T>::cgx(me, g);
+        acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
+      }
+      // y: NND difference from the carried rows; advance the state.
+      const T fnew = cur[i];
+      if (sy > 0) {
+        const T dn = fnew - f;
+        const T sk = slope_pos<LIM>(y1[i], dn);
+        const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
+        acc = fma(-Tab<T>::cgy(me, g), Dy, acc);
+        c[i] = fnew;
+        y1[i] = dn;
+        y2[i] = sk;
+      } else if (sy < 0) {
+        const T n1 = y1[i];
+        const T dlo = n1 - f, dhi = fnew - n1;
+        const T tk1 = slope_neg<LIM>(dlo, dhi);
+        const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
+        acc = fma(Tab<T>::cgy(me, g), Dy, acc);
+        c[i] = n1;
+        y1[i] = fnew;
+        y2[i] = tk1;
+      } else {
+        c[i] = fnew;
+      }
+      T res = fma(om, df[i], acc);
+      if constexpr (RKC) res = fma(alpha, fnv[i], beta * res);
+      if (writer)
+        *(T __attribute__((address_space(1))) *)(fout + ((uint32_t)i * pl + (uint32_t)(rk + col)) *
+                                                            (uint32_t)sizeof(T)) = res;
+    }
+  };
+
+  T bufA[kNV], bufB[kNV];
+  issue(y0, bufA);
+  for (int k = y0; k < yend; k += 2) {
+    row(k, bufA, bufB);
+    if (k + 1 < yend) row(k + 1, bufB, bufA);
   }
 }
 
+// Minimum resident wavefronts per SIMD requested from the register allocator.
+#ifndef DBM_MIN_WAVES_F32
+#define DBM_MIN_WAVES_F32 2
+#endif
+#ifndef DBM_MIN_WAVES_F64
+#define DBM_MIN_WAVES_F64 1
+#endif
+template <typename T> struct Occ;
+template <> struct Occ<float> { static constexpr int kMinWaves = DBM_MIN_WAVES_F32; };
+template <> struct Occ<double> { static constexpr int kMinWaves = DBM_MIN_WAVES_F64; };
+
+// One workgroup = S wavefronts, wavefront w advancing species w of a tile;
+// tiles are taken persistently from the table in XCD-grouped order.
 template <typename T, int S, int LIM, bool RKC>
-__global__ __launch_bounds__(kWave) void k_fused_stage(const InstDev *__restrict__ insts,
-                                                       const Tile *__restrict__ tiles,
-                                                       int ntiles, int in_idx, int fn_idx,
-                                                       int out_idx, T alpha, T beta) {
+__global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
+                                                           const Tile *__restrict__ tiles,
+                                                           int ntiles, int in_idx, int fn_idx,
+                                                           int out_idx, T alpha, T beta) {
+  __shared__ double mom[2][4 * S][kWave];
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[xcd_remap(v, ntiles)];
-    fused_tile<T, S, LIM, RKC>(insts[t.inst], t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
-                               alpha, beta);
+    fused_tile<T, S, LIM, RKC>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
+                               alpha, beta, mom);
+    __syncthreads();
   }
 }
 
@@ -527,11 +689,13 @@ __device__ __forceinline__ int map_axis(int j, int n, int bc, int &flips) {
     return q < 0 ? q + n : q;
   }
   if (bc == BC_OUTFLOW) return j < 0 ? 0 : n - 1;
-  for (int it = 0; it < 64 && (j < 0 || j >= n); ++it) {
-    j = (j < 0) ? (-1 - j) : (2 * n - 1 - j);
+  int q = j % (2 * n);
+  if (q < 0) q += 2 * n;
+  if (q >= n) {
     flips ^= 1;
+    return 2 * n - 1 - q;
   }
-  return j < 0 ? 0 : (j >= n ? n - 1 : j);
+  return q;
 }
 
 template <typename T>
@@ -859,7 +1023,7 @@ template <typename T, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                                  int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                                  hipStream_t st) {
-  hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave), 0, st, insts,
+  hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave * S), 0, st, insts,
                      tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta);
   return hipGetLastError();
 }
@@ -923,7 +1087,7 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, int *waves_per_c
                  default: return hipErrorInvalidValue; }
   }
 #undef DBM_PICK
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave, 0);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S, 0);
 }
 
 static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }

@@ -128,6 +128,8 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
   sp.tau = in.tau;
   sp.a = in.a_stoich;
   sp.inv_m = 1.0 / in.m;
+  sp.inv_neg_a = in.a_stoich < 0 ? -1.0 / in.a_stoich : 0.0;
+  sp.inv_K = 1.0 / sp.K;
   sp.omega = cfg.dt / in.tau;
   double vx[kNV], vy[kNV], et[kNV];
   for (int g = 0; g < 4; ++g) {
@@ -221,6 +223,12 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
   for (int k = 0; k < 4; ++k) {
     sp.KB1[k] = 0.25 * iB1[k];
     sp.KB2[k] = 0.25 * iB2[k];
+    sp.MB1[k] = mB1[k];
+    sp.MB2[k] = mB2[k];
+  }
+  for (int k = 0; k < 16; ++k) {
+    sp.MA[k] = mA[k];
+    sp.ME[k] = mE[k];
   }
   // Self-check: the block projection equals the dense inverse.
   for (int trial = 0; trial < 4; ++trial) {
@@ -262,10 +270,14 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
   for (int k = 0; k < 16; ++k) {
     sp.KA_f[k] = (float)sp.KA[k];
     sp.KE_f[k] = (float)sp.KE[k];
+    sp.MA_f[k] = (float)sp.MA[k];
+    sp.ME_f[k] = (float)sp.ME[k];
   }
   for (int k = 0; k < 4; ++k) {
     sp.KB1_f[k] = (float)sp.KB1[k];
     sp.KB2_f[k] = (float)sp.KB2[k];
+    sp.MB1_f[k] = (float)sp.MB1[k];
+    sp.MB2_f[k] = (float)sp.MB2[k];
   }
   return DBM_OK;
 }
