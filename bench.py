@@ -1,0 +1,218 @@
+"""Benchmark of the D2V16 multi-component DBM step on one MI355X.
+
+Workload (default): the three-species reacting premix on a 256x256 periodic
+grid (fuel/oxidiser/product, molar masses 2, 32, 18; one-step Arrhenius
+reaction k = 1e3 exp(-10/T); hot Gaussian kernel T = 3, sigma = 10 cells;
++-1% seeded density noise; dt = 1e-5, tau = 2e-5), FP32-bulk storage, forward
+Euler + NND (the paper's scheme).  A "step" is one full time step of the
+update: convection, moments, equilibrium, BGK + reaction + force, combine.
+
+Prints ONE JSON line.  `value` is cell-species updates per second over the K
+timed steps (graph-replayed, inputs resident in HBM).  `roofline` is for the
+one-pass stage kernel: algorithmic bytes (32 values of f read+written per
+cell-species per step) over its mean launch duration, measured here with HIP
+events recorded on the library's stream around eager launches.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload on this host.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --mode traffic --workload c4   (for rocprofv3 --pmc)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "cell·species updates/s + % HBM peak, FP32-bulk vs FP64 at stated L∞ error"
+UNIT = "cell-species updates/s"
+
+# HBM bytes per launch of the one-pass stage kernel, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs (profiles/fused_stage_traffic.md), keyed by
+# workload, with the hash of the kernel source they were taken at.  A changed
+# kernel source makes the entry stale and `traffic` is reported as null.
+MEASURED_TRAFFIC = {}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("dbm_kernels.hip", "dbm_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2006_15932_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str, precision: str):
+    from paper_2006_15932_amd import workloads as W
+    if name == "c1":
+        return W.reacting(n=256, steps=5000, precision=precision), (
+            "C1: 3-species reacting premix, 256x256 periodic, Euler+NND, dt=1e-5, tau=2e-5")
+    if name == "c2":
+        return W.rayleigh_taylor(n=1024, steps=20000, precision=precision), (
+            "C2: 4-species Rayleigh-Taylor, 1024x1024, walls in y, g=(0,-0.1), Euler+NND")
+    if name == "c4":
+        return W.shear_layer(n=4096, steps=5000, precision=precision), (
+            "C4: 4-species reacting supersonic double shear layer, 4096x4096 periodic, Euler+NND")
+    raise SystemExit("unknown workload " + name)
+
+
+def bytes_per_csu(precision: str, scheme: int) -> int:
+    es = 4 if precision == "fp32" else 8
+    return es * (32 if scheme == 0 else 128)
+
+
+def gpu_run(p, precision, steps, warmup, tile_rows=0):
+    import torch
+    from paper_2006_15932_amd import dbm as D
+    sim = D.Simulation(p, precision=precision)
+    assert sim.get_option(D.DBM_OPT_PATH) == 0, "one-pass HIP path not active"
+    if tile_rows:
+        sim.set_option(D.DBM_OPT_TILE_ROWS, tile_rows)
+    sim.set_fields()
+    sim.step(warmup)
+    sim.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(sim.stream)
+    sim.step(steps)
+    stop.record(sim.stream)
+    stop.synchronize()
+    ms = start.elapsed_time(stop)
+    kern_ms = sim.time_stage_kernel(20)
+    rows = sim.get_option(D.DBM_OPT_TILE_ROWS)
+    return sim, ms, kern_ms, rows
+
+
+def errors_vs_oracle(n=64, steps=200):
+    """FP32-bulk and FP64 runs of the same setup on an n x n instance against
+    the FP64 CPU oracle (relative L-infinity per field)."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from gpu_helpers import field_errors, oracle_run
+    from paper_2006_15932_amd import dbm as D
+    from paper_2006_15932_amd import workloads as W
+    p = W.reacting(n=n, steps=steps)
+    o, fo = oracle_run(p, steps)
+    mo = o.moments(fo)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        sim = D.Simulation(p, precision=prec)
+        sim.set_fields()
+        sim.step(steps)
+        e = field_errors(p, sim.moments(), mo)
+        out[prec] = {k: float("%.3e" % e[k]) for k in ("rho", "u", "T")}
+        sim.close()
+    return out
+
+
+def cpu_baseline(p, target_s=12.0):
+    from oracle import oracle as O
+    from paper_2006_15932_amd import workloads as W
+    threads = max(1, min(16, os.cpu_count() or 1))
+    O.set_threads(threads)
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    t0 = time.perf_counter()
+    f = o.run(f, 5)
+    est = (time.perf_counter() - t0) / 5
+    n = max(5, int(target_s / max(est, 1e-6)))
+    t0 = time.perf_counter()
+    o.run(f, n)
+    dt = time.perf_counter() - t0
+    return {"value": p.S * p.cells * n / dt, "unit": UNIT, "cores": threads, "kind": "oracle",
+            "sample": "FP64 oracle, %d Euler steps of the full %dx%d, %d-species workload "
+                      "(%.1f s)" % (n, p.nx, p.ny, p.S, dt)}
+
+
+def traffic_mode(args):
+    """Eager launches of the stage kernel plus a copy of known size, for
+    rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs."""
+    import torch
+    p, _ = workload(args.workload, args.precision)
+    sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows)
+    sim.time_stage_kernel(args.steps)
+    n = 256 << 20
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "traffic", "workload": args.workload, "rows": rows,
+                      "copy_bytes_each_way": n, "launches": args.steps}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2", "c4"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--mode", default="bench", choices=["bench", "traffic"])
+    ap.add_argument("--tile-rows", type=int, default=0, help="pin rows per tile (0 = autotune)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.mode == "traffic":
+        return traffic_mode(args)
+
+    p, desc = workload(args.workload, args.precision)
+    sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows)
+    csu_step = p.S * p.cells
+    value = csu_step * args.steps / (ms * 1e-3)
+    bpl = csu_step * bytes_per_csu(args.precision, p.scheme)
+    achieved = bpl / (kern_ms * 1e-3) / 1e9
+    tr = MEASURED_TRAFFIC.get(args.workload + "/" + args.precision)
+    traffic = None
+    if tr and tr.get("source") == kernel_source_hash():
+        traffic = tr["bytes_per_launch"]
+    sim.close()
+    line = {
+        "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": desc, "grid": [p.nx, p.ny], "species": p.S,
+                   "precision": "FP32-bulk (FP64 moments/T and conserved-row collision)"
+                   if args.precision == "fp32" else "FP64", "scheme": "euler",
+                   "tile_rows": rows},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_fused_stage", "bytes_per_launch": bpl,
+                     "ms_per_launch": kern_ms},
+    }
+    if not args.no_extra:
+        extra = {}
+        p64, _ = workload(args.workload, "fp64")
+        s64, ms64, k64, _ = gpu_run(p64, "fp64", max(1, args.steps // 5), 20)
+        extra["fp64_value"] = csu_step * max(1, args.steps // 5) / (ms64 * 1e-3)
+        s64.close()
+        extra["linf_vs_oracle"] = {"sample": "64x64 instance of the same setup, 200 steps",
+                                   **errors_vs_oracle()}
+        pl, dl = workload("c4", "fp32")
+        sl, msl, kl, rl = gpu_run(pl, "fp32", 50, 5)
+        bl = pl.S * pl.cells * 128
+        extra["large_grid"] = {"workload": dl, "value": pl.S * pl.cells * 50 / (msl * 1e-3),
+                               "roofline": {"achieved": bl / (kl * 1e-3) / 1e9,
+                                            "frac": bl / (kl * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                            "ms_per_launch": kl, "tile_rows": rl}}
+        sl.close()
+        line["extra"] = extra
+    if not args.no_cpu:
+        from paper_2006_15932_amd import workloads as W
+        line["cpu_baseline"] = cpu_baseline(p.with_(precision="fp64"))
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -145,7 +145,7 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   L.flag_off = off;
   off = align_up(off + sizeof(int));
   L.probe_off = off;
-  off = align_up(off + sizeof(int) * 256);
+  off = align_up(off + sizeof(int) * 512);
   for (int b = 0; b < 3; ++b) L.buf_off[b].resize(ninst);
   L.scratch_off.resize(ninst);
   for (int k = 0; k < ninst; ++k) {
@@ -403,7 +403,7 @@ int run_probe(dbm_handle h) {
   std::lock_guard<std::mutex> g(g_probe_mu);
   if (g_probe_state != 0) return DBM_OK;
   int *d = (int *)(h->ws + h->L.probe_off);
-  int out[256];
+  int out[512];
   HIPCHK(launch_dpp_probe(d, h->stream));
   HIPCHK(hipMemcpyAsync(out, d, sizeof(out), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -413,6 +413,10 @@ int run_probe(dbm_handle h) {
       const int shr = out[128 * rep + l], shl = out[128 * rep + 64 + l];
       ok &= shr == (l == 0 ? -1 : l - 1);
       ok &= shl == (l == 63 ? -1 : l + 1);
+      // guard-lane forms of lane value l+1: lane 0 / lane 63 read 0
+      const int gr = out[256 + 128 * rep + l], gl = out[320 + 128 * rep + l];
+      ok &= gr == (l == 0 ? 0 : l);
+      ok &= gl == (l == 63 ? 0 : l + 2);
     }
   g_probe_state = ok ? 1 : -1;
   return DBM_OK;

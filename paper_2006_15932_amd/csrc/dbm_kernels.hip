@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "../../include/dbm.h"
 #include "dbm_internal.hpp"
@@ -81,7 +82,9 @@ template <> struct Tab<double> {
 // table values it points to are re-read from the scalar cache each row
 // instead of being held (and spilled) in scalar registers.
 template <typename P> __device__ __forceinline__ P launder(P p) {
+#ifndef DBM_NO_LAUNDER
   asm volatile("" : "+s"(p));
+#endif
   return p;
 }
 
@@ -89,6 +92,26 @@ template <typename P> __device__ __forceinline__ P launder(P p) {
 // shl1 the value of lane i+1; the lane with no source keeps `old`.
 constexpr int kDppWaveShl1 = 0x130;
 constexpr int kDppWaveShr1 = 0x138;
+
+// Guard-lane variants for the stencil: the lane with no source reads 0
+// (bound_ctrl), which lets the compiler fold the move into the consuming
+// VALU instruction as a DPP operand.  Only guard lanes see the 0.
+__device__ __forceinline__ float shr1(float src) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), kDppWaveShr1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float shl1(float src) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(src), kDppWaveShl1, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double shr1(double src) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(src), kDppWaveShr1, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(src), kDppWaveShr1, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double shl1(double src) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(src), kDppWaveShl1, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(src), kDppWaveShl1, 0xf, 0xf, true);
+  return __hiloint2double(hi, lo);
+}
 
 __device__ __forceinline__ float dpp_shr1(float src, float old) {
   return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src),
@@ -233,29 +256,6 @@ __device__ __forceinline__ void block_feq(SpC &sp, const T *r, T *f) {
   }
 }
 
-// FP64 raw moments n, j_x, j_y, E = sum f q of one species from its 16 values.
-template <typename T>
-__device__ __forceinline__ void species_moments(SpC &sp, const T *c, double &n,
-                                                double &jx, double &jy, double &E) {
-  n = jx = jy = E = 0.0;
-#pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const double c0 = (double)c[4 * g], c1 = (double)c[4 * g + 1], c2 = (double)c[4 * g + 2],
-                 c3 = (double)c[4 * g + 3];
-    const double A = (c0 + c2) + (c1 + c3);
-    double X, Y;
-    if ((g & 1) == 0) {
-      X = c0 - c2; Y = c1 - c3;
-    } else {
-      X = (c0 + c3) - (c1 + c2); Y = (c0 + c1) - (c2 + c3);
-    }
-    n += A;
-    jx = fma(sp.vg[g], X, jx);
-    jy = fma(sp.vg[g], Y, jy);
-    E = fma(sp.qg[g], A, E);
-  }
-}
-
 // Orbit components of one species' 16 values (plane order of Eq.15):
 // A = sum, B = alternating sum, X, Y = sums signed by v_x, v_y.
 template <typename T>
@@ -274,6 +274,23 @@ __device__ __forceinline__ void orbit_parts(const T *c, T *A, T *B, T *X, T *Y) 
   }
 }
 
+// FP64 raw moments of one species from its orbit sums (see orbit_parts):
+// n = sum_g A_g, j = sum_g v_g (X_g, Y_g), E = sum_g q_g A_g.  The sums over
+// groups, which feed the temperature's cancellation, are done in FP64.
+template <typename T>
+__device__ __forceinline__ void species_moments(SpC &sp, const T *A, const T *X, const T *Y,
+                                                double &n, double &jx, double &jy, double &E) {
+  n = jx = jy = E = 0.0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const double a = (double)A[g];
+    n += a;
+    jx = fma(sp.vg[g], (double)X[g], jx);
+    jy = fma(sp.vg[g], (double)Y[g], jy);
+    E = fma(sp.qg[g], a, E);
+  }
+}
+
 // Per-cell scalar chain in FP64: mixture u and T from the species moments
 // (the conservation statement under Eq.6 with Eqs.8-10), then the one-step
 // reaction of Eqs.(1)-(2) within tau (Eq.5): extent xi (n* = n + a xi) and
@@ -282,41 +299,56 @@ struct CellState {
   double ux, uy, Tst, xi;
 };
 
-template <int S>
-__device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp,
-                                           const double *n, const double *jx,
-                                           const double *jy, const double *E,
-                                           CellState &cs) {
-  double rho = 0, px = 0, py = 0, e = 0, kn = 0;
+// 1/x to within an ulp or so: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+// exp(-E_a/(R T)): FP64 in FP64 mode; in FP32-bulk mode the rate only sets a
+// source that is itself rounded to FP32, so it is evaluated in FP32.
+template <typename T> __device__ __forceinline__ double arrhenius(double x);
+template <> __device__ __forceinline__ double arrhenius<double>(double x) { return exp(x); }
+template <> __device__ __forceinline__ double arrhenius<float>(double x) {
+  return (double)__expf((float)x);
+}
+
+template <typename T, int S>
+__device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*mb)[kWave],
+                                           int lane, CellState &cs) {
+  double rho = 0, px = 0, py = 0, e = 0, kn = 0, nF = 0, nO = 0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    rho = fma(sp[s].m, n[s], rho);
-    px = fma(sp[s].m, jx[s], px);
-    py = fma(sp[s].m, jy[s], py);
-    e = fma(sp[s].m, E[s], e);
-    kn = fma(sp[s].K, n[s], kn);
+    const double n = mb[0 * S + s][lane];
+    rho = fma(sp[s].m, n, rho);
+    px = fma(sp[s].m, mb[1 * S + s][lane], px);
+    py = fma(sp[s].m, mb[2 * S + s][lane], py);
+    e = fma(sp[s].m, mb[3 * S + s][lane], e);
+    kn = fma(sp[s].K, n, kn);
   }
-  const double irho = 1.0 / rho;
+  const double irho = recip(rho);
   cs.ux = px * irho;
   cs.uy = py * irho;
-  const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) / kn;
+  const double ikn = recip(kn);
+  const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) * ikn;
   cs.Tst = Tm;
   cs.xi = 0.0;
   if (I.react) {
-    double nF = 0.0, nO = 0.0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-      if (s == I.fuel) nF = fmax(n[s], 0.0);
-      if (s == I.oxid) nO = fmax(n[s], 0.0);
+      if (s == I.fuel) nF = fmax(mb[0 * S + s][lane], 0.0);
+      if (s == I.oxid) nO = fmax(mb[0 * S + s][lane], 0.0);
     }
-    double xi = I.k_ov * nF * nO * exp(-I.EaR / Tm) * sp[0].tau;
+    double xi = I.k_ov * nF * nO * arrhenius<T>(-I.EaR * recip(Tm)) * sp[0].tau;
+    double dkn = 0.0;
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      if (sp[s].a < 0.0) xi = fmin(xi, fmax(n[s], 0.0) * sp[s].inv_neg_a);
-    double kns = 0.0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) kns = fma(sp[s].K, fma(sp[s].a, xi, n[s]), kns);
-    cs.Tst = fma(Tm, kn, I.Q2 * xi) / kns;
+    for (int s = 0; s < S; ++s) {
+      if (sp[s].a < 0.0) xi = fmin(xi, fmax(mb[0 * S + s][lane], 0.0) * sp[s].inv_neg_a);
+      dkn = fma(sp[s].K, sp[s].a, dkn);
+    }
+    // sum (D+I) n* = kn + xi sum (D+I) a
+    cs.Tst = fma(Tm, kn, I.Q2 * xi) * recip(fma(xi, dkn, kn));
     cs.xi = xi;
   }
 }
@@ -329,10 +361,10 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp,
 // so the update conserves them to the rounding of the (small) difference
 // itself; the other rows are differenced in the storage precision.
 template <typename T>
-__device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp,
-                                                const T *c, double n, double jx, double jy,
-                                                double E, double ns, double ux, double uy,
-                                                double Tst, T *df) {
+__device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const T *A,
+                                                const T *B, const T *X, const T *Y, double n,
+                                                double jx, double jy, double E, double ns,
+                                                double ux, double uy, double Tst, T *df) {
   const double K = sp.K, th = Tst * sp.inv_m, u2 = ux * ux + uy * uy;
   T r[16];
   eq_rhs<T>((T)ns, (T)ux, (T)uy, (T)th, (T)K, r);
@@ -356,8 +388,6 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp,
     d8 += fd[8];
     d12 += fd[12];
   }
-  T A[4], B[4], X[4], Y[4];
-  orbit_parts<T>(c, A, B, X, Y);
   const T DBM_CONST *MA = Tab<T>::MA(sp), *MB1 = Tab<T>::MB1(sp), *MB2 = Tab<T>::MB2(sp),
                     *ME = Tab<T>::ME(sp);
   T d[16];
@@ -408,6 +438,13 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 // out = alpha * f^n + beta * (f + dt (C(f) + S(f)))   (RKC)
 // out = f + dt (C(f) + S(f))                          (!RKC)
 // ---------------------------------------------------------------------------
+// Rows of loads kept in flight per wavefront.
+#ifndef DBM_PREFETCH
+#define DBM_PREFETCH 3
+#endif
+constexpr int kPrefetch = DBM_PREFETCH;
+static_assert(kPrefetch >= 2, "the prefetch ring needs two or more slots");
+
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0-2 .. x0+61, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
@@ -477,8 +514,11 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     for (int i = 0; i < kNV; ++i) dst[i] = plane_sy(i) < 0 ? load(i, rb, fb) : load(i, ra, fa);
   };
 
-  auto row = [&](int k, const T *cur, T *nxt) {
-    if (k + 1 < yend) issue(k + 1, nxt);             // two rows in flight
+  // Row k consumes ring slot d and refills the slot freed by row k-1 with the
+  // values of row k+D-1, so D rows of loads are in flight.
+  T ring[kPrefetch][kNV];
+  auto row = [&](int k, const T *cur, T *refill) {
+    if (k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill);
     const int rk = k * nx;
     SpC *sp = launder(as_const(I.sp));
     SpC &me = sp[s];
@@ -488,27 +528,21 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       for (int i = 0; i < kNV; ++i) fnv[i] = at(fnb, (uint32_t)i * pl + (uint32_t)(rk + lcol));
     }
     // Own species' FP64 moments to LDS; one barrier; everyone's back.
+    T oA[4], oB[4], oX[4], oY[4];
+    orbit_parts<T>(c, oA, oB, oX, oY);
     double n0, jx0, jy0, E0;
-    species_moments<T>(me, c, n0, jx0, jy0, E0);
+    species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
     double(*mb)[kWave] = mom[k & 1];
     mb[0 * S + s][lane] = n0;
     mb[1 * S + s][lane] = jx0;
     mb[2 * S + s][lane] = jy0;
     mb[3 * S + s][lane] = E0;
     __syncthreads();
-    double n[S], jx[S], jy[S], E[S];
-#pragma unroll
-    for (int j = 0; j < S; ++j) {
-      n[j] = mb[0 * S + j][lane];
-      jx[j] = mb[1 * S + j][lane];
-      jy[j] = mb[2 * S + j][lane];
-      E[j] = mb[3 * S + j][lane];
-    }
     CellState cs;
-    cell_chain<S>(I, sp, n, jx, jy, E, cs);
+    cell_chain<T, S>(I, sp, mb, lane, cs);
     T df[kNV];
-    collision_delta<T>(I, me, c, n0, jx0, jy0, E0, fma(me.a, cs.xi, n0), cs.ux, cs.uy, cs.Tst,
-                       df);
+    collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, fma(me.a, cs.xi, n0), cs.ux,
+                       cs.uy, cs.Tst, df);
     const T om = Tab<T>::omega(me);
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
@@ -516,17 +550,19 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       const T f = c[i];
       T acc = f;
       // x: NND difference from adjacent lanes.
+      // Differences and limited slopes of the neighbouring lanes are the
+      // same quantities one lane over, so each is formed once and shifted.
       if (sx != 0) {
-        const T fm1 = dpp_shr1(f, f), fp1 = dpp_shl1(f, f);
+        const T dp = shl1(f) - f;                    // f_{j+1} - f_j
         T Dx;
         if (sx > 0) {
-          const T fm2 = dpp_shr1(fm1, fm1);
-          const T d0 = f - fm1, dp = fp1 - f, dm = fm1 - fm2;
-          Dx = d0 + T(0.5) * (slope_pos<LIM>(d0, dp) - slope_pos<LIM>(dm, d0));
+          const T d0 = shr1(dp);                     // f_j - f_{j-1}
+          const T sl = slope_pos<LIM>(d0, dp);       // limited slope at j
+          Dx = fma(T(0.5), sl - shr1(sl), d0);
         } else {
-          const T fp2 = dpp_shl1(fp1, fp1);
-          const T dlo = fp1 - f, dhi = fp2 - fp1, dm = f - fm1;
-          Dx = dlo - T(0.5) * (slope_neg<LIM>(dlo, dhi) - slope_neg<LIM>(dm, dlo));
+          const T dhi = shl1(dp);                    // f_{j+2} - f_{j+1}
+          const T sl = slope_neg<LIM>(dp, dhi);      // limited slope at j+1
+          Dx = fma(T(-0.5), sl - shr1(sl), dp);
         }
         const T cx = Tab<T>::cgx(me, g);
         acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
@@ -561,11 +597,13 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     }
   };
 
-  T bufA[kNV], bufB[kNV];
-  issue(y0, bufA);
-  for (int k = y0; k < yend; k += 2) {
-    row(k, bufA, bufB);
-    if (k + 1 < yend) row(k + 1, bufB, bufA);
+#pragma unroll
+  for (int d = 0; d < kPrefetch - 1; ++d)
+    if (y0 + d < yend) issue(y0 + d, ring[d]);
+  for (int k = y0; k < yend; k += kPrefetch) {
+#pragma unroll
+    for (int d = 0; d < kPrefetch; ++d)
+      if (k + d < yend) row(k + d, ring[d], ring[(d + kPrefetch - 1) % kPrefetch]);
   }
 }
 
@@ -586,11 +624,12 @@ template <typename T, int S, int LIM, bool RKC>
 __global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
                                                            const Tile *__restrict__ tiles,
                                                            int ntiles, int in_idx, int fn_idx,
-                                                           int out_idx, T alpha, T beta) {
+                                                           int out_idx, T alpha, T beta,
+                                                           int remap) {
   __shared__ double mom[2][4 * S][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-    const Tile t = tiles[xcd_remap(v, ntiles)];
+    const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
     fused_tile<T, S, LIM, RKC>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
                                alpha, beta, mom);
     __syncthreads();
@@ -1004,6 +1043,10 @@ __global__ __launch_bounds__(64) void k_dpp_probe(int *__restrict__ out) {
   const double d = (double)l;
   out[128 + l] = (int)dpp_shr1(d, -1.0);
   out[192 + l] = (int)dpp_shl1(d, -1.0);
+  out[256 + l] = (int)shr1(v + 1.0f);
+  out[320 + l] = (int)shl1(v + 1.0f);
+  out[384 + l] = (int)shr1(d + 1.0);
+  out[448 + l] = (int)shl1(d + 1.0);
 }
 
 // A single wavefront that idles for `ticks` of the constant-rate wall clock
@@ -1019,12 +1062,23 @@ __global__ __launch_bounds__(64) void k_delay(unsigned long long ticks) {
 // ---------------------------------------------------------------------------
 // Host-side launchers (called from dbm_api.cpp)
 // ---------------------------------------------------------------------------
+// Tile order: XCD-grouped (1, default) or plain dispatch order (0, for
+// comparison; DBM_XCD_REMAP=0 in the environment).
+static int g_xcd_remap = -1;
+static int xcd_remap_flag() {
+  if (g_xcd_remap < 0) {
+    const char *e = getenv("DBM_XCD_REMAP");
+    g_xcd_remap = (e && e[0] == '0') ? 0 : 1;
+  }
+  return g_xcd_remap;
+}
+
 template <typename T, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                                  int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                                  hipStream_t st) {
   hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave * S), 0, st, insts,
-                     tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta);
+                     tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta, g_xcd_remap);
   return hipGetLastError();
 }
 
@@ -1063,6 +1117,7 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
 hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st) {
+  xcd_remap_flag();
   return fp32 ? launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
                                       out_idx, alpha, beta, st)
               : launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
