@@ -590,7 +590,9 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         c[i] = fnew;
       }
       T res = fma(om, df[i], acc);
-      if constexpr (RKC) res = fma(alpha, fnv[i], beta * res);
+      // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
+      // the (small) stage difference
+      if constexpr (RKC) res = fma(alpha, fnv[i] - res, res);
       if (writer)
         *(T __attribute__((address_space(1))) *)(fout + ((uint32_t)i * pl + (uint32_t)(rk + col)) *
                                                             (uint32_t)sizeof(T)) = res;
@@ -791,7 +793,7 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   }
   const T feq = ((const T *)I.scratch)[(size_t)si * plane + cell];
   T res = fc + C + (T)sp.omega * (feq - fc);
-  if (rkc) res = alpha * ((const T *)I.buf[fn_idx])[(size_t)si * plane + cell] + beta * res;
+  if (rkc) res = fma(alpha, ((const T *)I.buf[fn_idx])[(size_t)si * plane + cell] - res, res);
   ((T *)I.buf[out_idx])[(size_t)si * plane + cell] = res;
 }
 

@@ -1,0 +1,90 @@
+"""Parity at full workload sizes, in the launch configuration the benchmark
+uses (autotuned tiles, graph replay), on sampled cells.
+
+After K steps a cell depends only on the cells within 2K of it (the NND
+stencil reaches two cells per step), so the oracle evolves a (4K+5)^2 window
+of the same seeded initial fields around each sample (wrapping periodically,
+outflow at the window edge, which cannot reach the centre in K steps) and the
+centre is compared with the GPU result.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2006_15932_amd import dbm as D
+from paper_2006_15932_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _samples(p, k, seed, margin_y=0):
+    r = W.splitmix64(seed, 2 * k)
+    pts = [(0, margin_y), (p.nx - 1, p.ny - 1 - margin_y), (59, p.ny // 2), (60, p.ny // 2 + 1),
+           (119, margin_y + 3), (p.nx // 2, p.ny // 2)]
+    for j in range(k):
+        x = int(r[2 * j] * p.nx)
+        y = margin_y + int(r[2 * j + 1] * (p.ny - 2 * margin_y))
+        pts.append((x, min(y, p.ny - 1 - margin_y)))
+    return pts
+
+
+def _check(p, precision, steps, tol, nsamples=10, margin_y=0):
+    print("full-size", p.name, p.nx, p.ny, precision, "steps", steps, flush=True)
+    sim = D.Simulation(p, precision=precision)
+    sim.set_fields()
+    sim.step(steps)
+    rho, ux, uy, T = sim.moments()
+    sim.close()
+    O.set_threads(8)
+    w = 4 * steps + 5
+    worst = {"rho": 0.0, "u": 0.0, "T": 0.0}
+    for (x, y) in _samples(p, nsamples, 4242 + steps, margin_y):
+        q = W.window(p, x, y, w)
+        o = O.Oracle(q)
+        f = o.run(o.init_equilibrium(*W.fields(q)), steps)
+        ro, uxo, uyo, To = o.moments(f)
+        c = w // 2
+        r_g, r_o = rho[:, y, x].sum(), ro[:, c, c].sum()
+        n_o = sum(ro[s, c, c] / p.species[s].m for s in range(p.S))
+        cs = math.sqrt(1.4 * To[c, c] / (r_o / n_o))
+        worst["rho"] = max(worst["rho"], abs(r_g - r_o) / abs(r_o))
+        worst["T"] = max(worst["T"], abs(T[y, x] - To[c, c]) / abs(To[c, c]))
+        du = math.hypot(ux[y, x] - uxo[c, c], uy[y, x] - uyo[c, c])
+        worst["u"] = max(worst["u"], du / max(math.hypot(uxo[c, c], uyo[c, c]), cs))
+    print("worst sampled errors", worst, flush=True)
+    for k, v in worst.items():
+        assert v < tol, (k, v, worst)
+
+
+def test_shear_layer_4096_fp32_sampled():
+    _check(W.shear_layer(n=4096, precision="fp32"), "fp32", 4, 1e-5)
+
+
+def test_rayleigh_taylor_1024_fp32_sampled():
+    # walls in y: samples stay outside the walls' light cone
+    _check(W.rayleigh_taylor(n=1024, precision="fp32"), "fp32", 4, 1e-5, margin_y=2 * 4 + 3)
+
+
+def test_reacting_256_fp64_sampled():
+    _check(W.reacting(n=256, precision="fp64"), "fp64", 20, 1e-10)
+
+
+def test_batched_uneven_fp32_subset_within_1e5():
+    """C3-style batch (uneven sizes, per-instance tau and hot-spot T) in one
+    persistent launch per stage, FP32-bulk, against the oracle per instance."""
+    import sys
+    sys.path.insert(0, __file__.rsplit("/", 1)[0])
+    from gpu_helpers import field_errors, oracle_run
+    probs = W.batch(count=8, sizes=(32, 64, 96, 128), steps=200, precision="fp32")
+    sim = D.Simulation(probs, precision="fp32")
+    for k in range(len(probs)):
+        sim.set_fields(k)
+    sim.step(200)
+    for k, p in enumerate(probs):
+        o, fo = oracle_run(p, 200)
+        e = field_errors(p, sim.moments(k), o.moments(fo))
+        print("batch instance", k, p.nx, e, flush=True)
+        for key in ("rho", "u", "T"):
+            assert e[key] < 1e-5, (k, key, e)

@@ -139,8 +139,9 @@ def test_checkpoint_restart_is_bit_exact():
         np.testing.assert_array_equal(a.get_f(), c.get_f())
 
 
-def test_fp32_bulk_reacting_within_1e5():
-    p = W.reacting(n=64, steps=500, precision="fp32")
+@pytest.mark.parametrize("scheme", [W.EULER, W.RK3])
+def test_fp32_bulk_reacting_within_1e5(scheme):
+    p = W.reacting(n=64, steps=500, precision="fp32", scheme=scheme)
     sim = gpu_run(p, 500, "fp32")
     o, fo = oracle_run(p, 500)
     errs = field_errors(p, sim.moments(), o.moments(fo))
