@@ -62,7 +62,7 @@ int fail(int code, const std::string &msg) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-constexpr int kTilesPerRowStride = 60;  // output columns per wavefront tile
+constexpr int kTilesPerRowStride = 64;  // columns per tile (one per lane)
 
 int tiles_x(int nx) { return (nx + kTilesPerRowStride - 1) / kTilesPerRowStride; }
 

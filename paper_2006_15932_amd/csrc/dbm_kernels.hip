@@ -5,11 +5,13 @@
 // FP64), x fastest, so every velocity plane is a dense 2-D array and a
 // wavefront's 64 lanes read 64 consecutive cells of one plane per load.
 //
-// The one-pass stage kernel (k_fused_stage) gives each wavefront a tile of
-// 60 output columns (64 lanes with two guard lanes on each side) by `rows`
-// rows and marches it in +y:
+// The one-pass stage kernel (k_fused_stage) gives each workgroup a tile of 64
+// columns (one per lane, 128-byte aligned) by `rows` rows, one wavefront per
+// species, and marches it in +y:
 //   * x-neighbours of the NND stencil come from adjacent lanes through DPP
-//     whole-wavefront shifts (no LDS, no barriers);
+//     whole-wavefront shifts (no LDS, no barriers); the three values beyond
+//     the tile's edges that each x-moving plane needs arrive in one compact
+//     load per row (36 lanes) and enter the shifts at the edge lanes;
 //   * y-neighbours are carried in registers from row to row (three values per
 //     plane with a nonzero v_y, one prefetched value for the others), so each
 //     value of f is loaded once per tile plus a four-row halo;
@@ -18,7 +20,7 @@
 //     is formed through the symmetry blocks of M (56 multiply-adds instead of
 //     256) before the BGK + source + Runge-Kutta combine and a single store.
 // Tiles are taken from a table in an order that keeps x-neighbouring tiles on
-// the same XCD (one L2 per XCD) so that the guard columns hit in L2.
+// the same XCD (one L2 per XCD) so that the halo columns hit in L2.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -133,6 +135,23 @@ __device__ __forceinline__ double dpp_shl1(double src, double old) {
                                        0xf, 0xf, false);
   int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), kDppWaveShl1,
                                        0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Stencil shifts with the edge lane fed from `edge` (a value of the
+// neighbouring tile): lane 0 of shr1e and lane 63 of shl1e return `edge`.
+__device__ __forceinline__ float shr1e(float src, float edge) { return dpp_shr1(src, edge); }
+__device__ __forceinline__ float shl1e(float src, float edge) { return dpp_shl1(src, edge); }
+__device__ __forceinline__ double shr1e(double src, double edge) { return dpp_shr1(src, edge); }
+__device__ __forceinline__ double shl1e(double src, double edge) { return dpp_shl1(src, edge); }
+
+// Value of lane l (a compile-time constant) broadcast to the wavefront.
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
   return __hiloint2double(hi, lo);
 }
 
@@ -440,13 +459,28 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 // ---------------------------------------------------------------------------
 // Rows of loads kept in flight per wavefront.
 #ifndef DBM_PREFETCH
-#define DBM_PREFETCH 3
+#define DBM_PREFETCH 2
 #endif
 constexpr int kPrefetch = DBM_PREFETCH;
 static_assert(kPrefetch >= 2, "the prefetch ring needs two or more slots");
 
+// The 12 planes with a nonzero v_x, in plane order, and the halo columns each
+// needs: x0-1 and x0+64 always, and x0-2 (v_x > 0) or x0+65 (v_x < 0).
+__host__ __device__ constexpr int xplane(int j) {
+  return j < 2 ? 2 * j : (j < 6 ? j + 2 : (j < 8 ? 2 * j - 4 : j + 4));
+}
+__host__ __device__ constexpr int xplane_index(int i) {
+  return i < 4 ? i / 2 : (i < 8 ? i - 2 : (i < 12 ? i / 2 + 2 : i - 4));
+}
+static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) == 10 &&
+                  xplane(8) == 12 && xplane(11) == 15 && xplane_index(10) == 7 &&
+                  xplane_index(13) == 9 && plane_sx(10) != 0 && plane_sx(9) == 0 && plane_sx(1) == 0,
+              "x-moving planes of the D2V16 ordering");
+constexpr int kXPlanes = 12;
+constexpr int kHaloLanes = 3 * kXPlanes;
+
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
-// x0-2 .. x0+61, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
+// x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
 template <typename T, int S, int LIM, bool RKC>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
@@ -466,15 +500,26 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   auto at = [&](gbytes b, uint32_t e) -> T {
     return *(const T __attribute__((address_space(1))) *)(b + e * (uint32_t)sizeof(T));
   };
-  const int col = x0 - 2 + lane;                   // column held by this lane
+  const int col = x0 + lane;                       // column held by this lane
   const int lcol = map_x(col, nx, I.bcx);          // where its value lives
-  const bool writer = lane >= 2 && lane < kWave - 2 && col < nx;
+  const bool writer = col < nx;
   const int yend = y0 + rows;
 
   auto load = [&](int i, int roff, bool flip) -> T {
     const uint32_t p = flip ? mirror_y(i) : i;
     return at(fin, p * pl + (uint32_t)(roff + lcol));
   };
+  // Compact halo: lane 3j+w (j < 12) holds plane xplane(j) at column x0-1
+  // (w = 0), x0-2 or x0+65 (w = 1, by the sign of v_x), x0+64 (w = 2).
+  // Lanes 36..63 re-read lane 0's value (in bounds, never used).
+  uint32_t hoff;
+  {
+    const int hl = lane < kHaloLanes ? lane : 0;
+    const int j = hl / 3, w = hl - 3 * j;
+    const int hp = xplane(j);
+    const int hcol = w == 0 ? x0 - 1 : (w == 2 ? x0 + kWave : (plane_sx(hp) > 0 ? x0 - 2 : x0 + kWave + 1));
+    hoff = (uint32_t)hp * pl + (uint32_t)map_x(hcol, nx, I.bcx);
+  }
 
   // State carried between rows, per plane i:
   //   c  = f at the current row k
@@ -506,27 +551,25 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     }
   }
 
-  // New values consumed by row k: row k+1 (v_y >= 0) or k+2 (v_y < 0).
-  auto issue = [&](int k, T *dst) {
+  // New values consumed by row k: row k+1 (v_y >= 0) or k+2 (v_y < 0), and
+  // the x-halo of row k itself (an interior row: no y mapping).
+  auto issue = [&](int k, T *dst, T &halo) {
     bool fa, fb;
     const int ra = map_y(k + 1, ny, bcy, fa) * nx, rb = map_y(k + 2, ny, bcy, fb) * nx;
 #pragma unroll
     for (int i = 0; i < kNV; ++i) dst[i] = plane_sy(i) < 0 ? load(i, rb, fb) : load(i, ra, fa);
+    halo = at(fin, hoff + (uint32_t)(k * nx));
   };
 
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
   // values of row k+D-1, so D rows of loads are in flight.
   T ring[kPrefetch][kNV];
-  auto row = [&](int k, const T *cur, T *refill) {
-    if (k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill);
+  T hring[kPrefetch];
+  auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
+    if (k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
     const int rk = k * nx;
     SpC *sp = launder(as_const(I.sp));
     SpC &me = sp[s];
-    T fnv[kNV];
-    if constexpr (RKC) {
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) fnv[i] = at(fnb, (uint32_t)i * pl + (uint32_t)(rk + lcol));
-    }
     // Own species' FP64 moments to LDS; one barrier; everyone's back.
     T oA[4], oB[4], oX[4], oY[4];
     orbit_parts<T>(c, oA, oB, oX, oY);
@@ -538,6 +581,12 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     mb[2 * S + s][lane] = jy0;
     mb[3 * S + s][lane] = E0;
     __syncthreads();
+    // f^n of the Runge-Kutta combine, loaded here to shorten its live range
+    T fnv[kNV];
+    if constexpr (RKC) {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) fnv[i] = at(fnb, (uint32_t)i * pl + (uint32_t)(rk + lcol));
+    }
     CellState cs;
     cell_chain<T, S>(I, sp, mb, lane, cs);
     T df[kNV];
@@ -552,17 +601,25 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
+      // Edge lanes take the tile's halo: lo1 = f(x0-1), hi1 = f(x0+64),
+      // w1 = f(x0-2) (v_x > 0) or f(x0+65) (v_x < 0).
       if (sx != 0) {
-        const T dp = shl1(f) - f;                    // f_{j+1} - f_j
+        const int j = xplane_index(i);
+        const T lo1 = readlane(hcur, 3 * j), w1 = readlane(hcur, 3 * j + 1);
+        const T hi1 = readlane(hcur, 3 * j + 2);
+        const T dp = shl1e(f, hi1) - f;              // f_{j+1} - f_j
+        const T dl = f - lo1;                        // lane 0: f_{x0} - f_{x0-1}
         T Dx;
         if (sx > 0) {
-          const T d0 = shr1(dp);                     // f_j - f_{j-1}
+          const T d0 = shr1e(dp, dl);                // f_j - f_{j-1}
           const T sl = slope_pos<LIM>(d0, dp);       // limited slope at j
-          Dx = fma(T(0.5), sl - shr1(sl), d0);
+          const T sle = slope_pos<LIM>(lo1 - w1, dl);  // lane 0: slope at x0-1
+          Dx = fma(T(0.5), sl - shr1e(sl, sle), d0);
         } else {
-          const T dhi = shl1(dp);                    // f_{j+2} - f_{j+1}
+          const T dhi = shl1e(dp, w1 - hi1);         // f_{j+2} - f_{j+1}
           const T sl = slope_neg<LIM>(dp, dhi);      // limited slope at j+1
-          Dx = fma(T(-0.5), sl - shr1(sl), dp);
+          const T sle = slope_neg<LIM>(dl, dp);      // lane 0: slope at x0
+          Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
         }
         const T cx = Tab<T>::cgx(me, g);
         acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
@@ -601,11 +658,14 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 
 #pragma unroll
   for (int d = 0; d < kPrefetch - 1; ++d)
-    if (y0 + d < yend) issue(y0 + d, ring[d]);
+    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d]);
   for (int k = y0; k < yend; k += kPrefetch) {
 #pragma unroll
-    for (int d = 0; d < kPrefetch; ++d)
-      if (k + d < yend) row(k + d, ring[d], ring[(d + kPrefetch - 1) % kPrefetch]);
+    for (int d = 0; d < kPrefetch; ++d) {
+      if (k + d < yend)
+        row(k + d, ring[d], hring[d], ring[(d + kPrefetch - 1) % kPrefetch],
+            hring[(d + kPrefetch - 1) % kPrefetch]);
+    }
   }
 }
 
