@@ -9,9 +9,10 @@ update: convection, moments, equilibrium, BGK + reaction + force, combine.
 
 Prints ONE JSON line.  `value` is cell-species updates per second over the K
 timed steps (graph-replayed, inputs resident in HBM).  `roofline` is for the
-one-pass stage kernel: algorithmic bytes (32 values of f read+written per
-cell-species per step) over its mean launch duration, measured here with HIP
-events recorded on the library's stream around eager launches.
+one-pass stage kernel, the only kernel of a step: algorithmic bytes (32
+values of f read+written per cell-species per Euler step) over its mean
+launch duration, which is the HIP-event time of the timed region (events
+recorded on the library's stream) divided by the launches in it.
 `cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
 workload on this host.
 
@@ -39,7 +40,10 @@ UNIT = "cell-species updates/s"
 # FETCH_SIZE and WRITE_SIZE runs (profiles/fused_stage_traffic.md), keyed by
 # workload, with the hash of the kernel source they were taken at.  A changed
 # kernel source makes the entry stale and `traffic` is reported as null.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {
+    "c1/fp32": {"source": "5dc97c9d32d506fe", "bytes_per_launch": 26488852},
+    "c4/fp32": {"source": "5dc97c9d32d506fe", "bytes_per_launch": 10363545647},
+}
 
 
 def kernel_source_hash() -> str:
@@ -85,7 +89,8 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0):
     stop.record(sim.stream)
     stop.synchronize()
     ms = start.elapsed_time(stop)
-    kern_ms = sim.time_stage_kernel(20)
+    launches = steps * (1 if p.scheme == 0 else 3)
+    kern_ms = ms / launches
     rows = sim.get_option(D.DBM_OPT_TILE_ROWS)
     return sim, ms, kern_ms, rows
 
@@ -186,6 +191,7 @@ def traffic_mode(args):
     p, _ = workload(args.workload, args.precision)
     sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows)
     sim.time_stage_kernel(args.steps)
+    sim.close()
     n = 256 << 20
     a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -216,6 +222,7 @@ def main():
         return traffic_mode(args)
 
     p, desc = workload(args.workload, args.precision)
+    assert p.scheme == 0, "one launch per step is assumed below"
     sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows)
     csu_step = p.S * p.cells
     value = csu_step * args.steps / (ms * 1e-3)

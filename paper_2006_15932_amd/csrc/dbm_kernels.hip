@@ -29,6 +29,11 @@
 #include "../../include/dbm.h"
 #include "dbm_internal.hpp"
 
+// Streaming (non-temporal) stores of the new distribution.
+#ifndef DBM_NT_STORE
+#define DBM_NT_STORE 1
+#endif
+
 namespace dbm {
 
 // ---------------------------------------------------------------------------
@@ -145,6 +150,35 @@ __device__ __forceinline__ float shl1e(float src, float edge) { return dpp_shl1(
 __device__ __forceinline__ double shr1e(double src, double edge) { return dpp_shr1(src, edge); }
 __device__ __forceinline__ double shl1e(double src, double edge) { return dpp_shl1(src, edge); }
 
+// Raw buffer access (MUBUF): a 128-bit resource holds the 64-bit base and the
+// byte size, the per-lane offset is a VGPR and a wavefront-uniform offset
+// (the plane) an SGPR, so a load costs no vector address arithmetic.
+// Accesses beyond the size return 0 / are dropped by the hardware.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // raw 32-bit data format (gfx9 family)
+__device__ __forceinline__ rsrc_t make_rsrc(const void *base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                           kRsrcWord3);
+}
+template <typename T> __device__ __forceinline__ T bload(rsrc_t r, uint32_t voff, uint32_t soff);
+template <> __device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <> __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+// Stores of the new distribution: aux bit 1 marks them non-temporal.
+constexpr int kStoreAux = DBM_NT_STORE ? 2 : 0;
+__device__ __forceinline__ void bstore(rsrc_t r, float v, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff,
+                                        kStoreAux);
+}
+__device__ __forceinline__ void bstore(rsrc_t r, double v, uint32_t voff, uint32_t soff) {
+  typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)voff, (int)soff,
+                                        kStoreAux);
+}
+
 // Value of lane l (a compile-time constant) broadcast to the wavefront.
 __device__ __forceinline__ float readlane(float v, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
@@ -152,6 +186,16 @@ __device__ __forceinline__ float readlane(float v, int l) {
 __device__ __forceinline__ double readlane(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Lane gather through the LDS crossbar: lane l gets v from lane addr[l] / 4.
+__device__ __forceinline__ float bperm(int addr, float v) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
+}
+__device__ __forceinline__ double bperm(int addr, double v) {
+  const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
   return __hiloint2double(hi, lo);
 }
 
@@ -391,12 +435,12 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const
   const bool force = I.force && n > 1e-300;
   double fd[16];
   if (force) {
-    const double inv_n = 1.0 / n;
+    const double inv_n = recip(n);
     const double us = jx * inv_n, vs = jy * inv_n;
-    const double Ts = sp.m * (E * inv_n - us * us - vs * vs) / K;
+    const double Ts = sp.m * (E * inv_n - us * us - vs * vs) * sp.inv_K;
     double Td = Ts;
     if (I.fmode == DBM_FORCE_T_EXACT)
-      Td = Ts - sp.m * sp.tau * sp.tau * (I.ax * I.ax + I.ay * I.ay) / K;
+      Td = Ts - sp.m * sp.tau * sp.tau * (I.ax * I.ax + I.ay * I.ay) * sp.inv_K;
     double r1[16], r2[16];
     eq_rhs<double>(n, us + sp.tau * I.ax, vs + sp.tau * I.ay, Td * sp.inv_m, K, r1);
     eq_rhs<double>(n, us, vs, Ts * sp.inv_m, K, r2);
@@ -479,6 +523,15 @@ static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) ==
 constexpr int kXPlanes = 12;
 constexpr int kHaloLanes = 3 * kXPlanes;
 
+// Halo distribution: LDS crossbar gather (1) or lane reads (0), per type.
+#ifndef DBM_GATHER_F32
+#define DBM_GATHER_F32 1
+#endif
+#ifndef DBM_GATHER_F64
+#define DBM_GATHER_F64 1
+#endif
+template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F32 : DBM_GATHER_F64;
+
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
@@ -488,18 +541,16 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
                                            T alpha, T beta, double (*mom)[4 * S][kWave]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
-  // One 64-bit base per species and buffer; everything below it is a 32-bit
-  // byte offset (the host keeps 16 planes of one species under 4 GiB).
+  // One buffer resource per species and buffer (its 16 planes, under 4 GiB
+  // by a host check); offsets below it are 32-bit byte counts: the plane in
+  // the SGPR offset, the cell in the VGPR offset.
+  constexpr uint32_t es = sizeof(T);
   const size_t plane = (size_t)nx * (size_t)ny;
-  const uint32_t pl = (uint32_t)plane;
-  typedef const char __attribute__((address_space(1))) *gbytes;
-  typedef char __attribute__((address_space(1))) *gbytes_mut;
-  const gbytes fin = (gbytes)(as_global<T>(I.buf[in_idx]) + (size_t)s * kNV * plane);
-  const gbytes fnb = (gbytes)(as_global<T>(I.buf[fn_idx]) + (size_t)s * kNV * plane);
-  const gbytes_mut fout = (gbytes_mut)(as_global_mut<T>(I.buf[out_idx]) + (size_t)s * kNV * plane);
-  auto at = [&](gbytes b, uint32_t e) -> T {
-    return *(const T __attribute__((address_space(1))) *)(b + e * (uint32_t)sizeof(T));
-  };
+  const uint32_t plb = (uint32_t)plane * es;       // bytes per plane
+  const uint32_t spb = kNV * plb;                  // bytes per species
+  const rsrc_t rin = make_rsrc((const T *)I.buf[in_idx] + (size_t)s * kNV * plane, spb);
+  const rsrc_t rfn = make_rsrc((const T *)I.buf[fn_idx] + (size_t)s * kNV * plane, spb);
+  const rsrc_t rout = make_rsrc((const T *)I.buf[out_idx] + (size_t)s * kNV * plane, spb);
   const int col = x0 + lane;                       // column held by this lane
   const int lcol = map_x(col, nx, I.bcx);          // where its value lives
   const bool writer = col < nx;
@@ -507,7 +558,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 
   auto load = [&](int i, int roff, bool flip) -> T {
     const uint32_t p = flip ? mirror_y(i) : i;
-    return at(fin, p * pl + (uint32_t)(roff + lcol));
+    return bload<T>(rin, (uint32_t)(roff + lcol) * es, p * plb);
   };
   // Compact halo: lane 3j+w (j < 12) holds plane xplane(j) at column x0-1
   // (w = 0), x0-2 or x0+65 (w = 1, by the sign of v_x), x0+64 (w = 2).
@@ -518,8 +569,11 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     const int j = hl / 3, w = hl - 3 * j;
     const int hp = xplane(j);
     const int hcol = w == 0 ? x0 - 1 : (w == 2 ? x0 + kWave : (plane_sx(hp) > 0 ? x0 - 2 : x0 + kWave + 1));
-    hoff = (uint32_t)hp * pl + (uint32_t)map_x(hcol, nx, I.bcx);
+    hoff = (uint32_t)hp * plb + (uint32_t)map_x(hcol, nx, I.bcx) * es;
   }
+  // Gather addresses of the halo: h1 puts slot 0 (x0-1) in lane 0 and slot 2
+  // (x0+64) in lane 63; h2 broadcasts slot 1.  Plane j adds 12 j bytes.
+  const int hidx1 = lane == kWave - 1 ? 8 : 0;
 
   // State carried between rows, per plane i:
   //   c  = f at the current row k
@@ -558,7 +612,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     const int ra = map_y(k + 1, ny, bcy, fa) * nx, rb = map_y(k + 2, ny, bcy, fb) * nx;
 #pragma unroll
     for (int i = 0; i < kNV; ++i) dst[i] = plane_sy(i) < 0 ? load(i, rb, fb) : load(i, ra, fa);
-    halo = at(fin, hoff + (uint32_t)(k * nx));
+    halo = bload<T>(rin, hoff + (uint32_t)(k * nx) * es, 0);
   };
 
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
@@ -585,7 +639,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     T fnv[kNV];
     if constexpr (RKC) {
 #pragma unroll
-      for (int i = 0; i < kNV; ++i) fnv[i] = at(fnb, (uint32_t)i * pl + (uint32_t)(rk + lcol));
+      for (int i = 0; i < kNV; ++i) fnv[i] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, i * plb);
     }
     CellState cs;
     cell_chain<T, S>(I, sp, mb, lane, cs);
@@ -601,22 +655,28 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
-      // Edge lanes take the tile's halo: lo1 = f(x0-1), hi1 = f(x0+64),
-      // w1 = f(x0-2) (v_x > 0) or f(x0+65) (v_x < 0).
+      // Edge lanes take the tile's halo: h1 = f(x0-1) in lane 0 and
+      // f(x0+64) in lane 63; h2 = f(x0-2) (v_x > 0) or f(x0+65) (v_x < 0).
       if (sx != 0) {
         const int j = xplane_index(i);
-        const T lo1 = readlane(hcur, 3 * j), w1 = readlane(hcur, 3 * j + 1);
-        const T hi1 = readlane(hcur, 3 * j + 2);
-        const T dp = shl1e(f, hi1) - f;              // f_{j+1} - f_j
-        const T dl = f - lo1;                        // lane 0: f_{x0} - f_{x0-1}
+        T h1, h2;
+        if constexpr (kHaloGather<T>) {
+          h1 = bperm(hidx1 + 12 * j, hcur);
+          h2 = bperm(4 + 12 * j, hcur);
+        } else {
+          h1 = lane == 0 ? readlane(hcur, 3 * j) : readlane(hcur, 3 * j + 2);
+          h2 = readlane(hcur, 3 * j + 1);
+        }
+        const T dp = shl1e(f, h1) - f;               // f_{j+1} - f_j
+        const T dl = f - h1;                         // lane 0: f_{x0} - f_{x0-1}
         T Dx;
         if (sx > 0) {
           const T d0 = shr1e(dp, dl);                // f_j - f_{j-1}
           const T sl = slope_pos<LIM>(d0, dp);       // limited slope at j
-          const T sle = slope_pos<LIM>(lo1 - w1, dl);  // lane 0: slope at x0-1
+          const T sle = slope_pos<LIM>(h1 - h2, dl);   // lane 0: slope at x0-1
           Dx = fma(T(0.5), sl - shr1e(sl, sle), d0);
         } else {
-          const T dhi = shl1e(dp, w1 - hi1);         // f_{j+2} - f_{j+1}
+          const T dhi = shl1e(dp, h2 - h1);          // lane 63: f_{x0+65} - f_{x0+64}
           const T sl = slope_neg<LIM>(dp, dhi);      // limited slope at j+1
           const T sle = slope_neg<LIM>(dl, dp);      // lane 0: slope at x0
           Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
@@ -650,9 +710,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
       // the (small) stage difference
       if constexpr (RKC) res = fma(alpha, fnv[i] - res, res);
-      if (writer)
-        *(T __attribute__((address_space(1))) *)(fout + ((uint32_t)i * pl + (uint32_t)(rk + col)) *
-                                                            (uint32_t)sizeof(T)) = res;
+      if (writer) bstore(rout, res, (uint32_t)(rk + col) * es, i * plb);
     }
   };
 
