@@ -95,6 +95,17 @@ template <typename P> __device__ __forceinline__ P launder(P p) {
   return p;
 }
 
+// The same, and also not before `v` is computed: the table values read
+// through the result are loaded where they are used, so that the scalar
+// registers hold one block of a table at a time.
+// Applied in FP64 only: the FP32 tables fit in scalar registers as they are.
+template <typename P, typename V> __device__ __forceinline__ P launder_after(P p, V v) {
+#ifndef DBM_NO_LAUNDER
+  if constexpr (sizeof(V) == 8) asm volatile("" : "+s"(p) : "v"(v));
+#endif
+  return p;
+}
+
 // DPP whole-wavefront shifts: shr1 gives lane i the value of lane i-1,
 // shl1 the value of lane i+1; the lane with no source keeps `old`.
 constexpr int kDppWaveShl1 = 0x130;
@@ -288,8 +299,10 @@ __device__ __forceinline__ void eq_rhs(U n, U ux, U uy, U th, U K, U *r) {
 // f^eq of one species from its block right-hand side (plane order of Eq.15).
 template <typename T>
 __device__ __forceinline__ void block_feq(SpC &sp, const T *r, T *f) {
-  const T DBM_CONST *KA = Tab<T>::KA(sp), *KB1 = Tab<T>::KB1(sp), *KB2 = Tab<T>::KB2(sp),
-                    *KE = Tab<T>::KE(sp);
+  const T DBM_CONST *KA = launder_after(Tab<T>::KA(sp), r[0]);
+  const T DBM_CONST *KE = launder_after(Tab<T>::KE(sp), r[8]);
+  const T DBM_CONST *KB1 = launder_after(Tab<T>::KB1(sp), r[4]);
+  const T DBM_CONST *KB2 = launder_after(Tab<T>::KB2(sp), r[6]);
   T al[4], xi[4], ps[4], be[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -362,11 +375,15 @@ struct CellState {
   double ux, uy, Tst, xi;
 };
 
-// 1/x to within an ulp or so: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double recip(double x) {
+// 1/x: hardware estimate refined by Newton steps (each squares the
+// relative error of the estimate): two in FP64 mode (to about an ulp), one in
+// FP32-bulk mode, where the result (relative error ~1e-14) only meets
+// FP32-rounded quantities.
+template <typename T> __device__ __forceinline__ double recip(double x) {
   double r = __builtin_amdgcn_rcp(x);
   r = fma(r, fma(-x, r, 1.0), r);
-  return fma(r, fma(-x, r, 1.0), r);
+  if constexpr (sizeof(T) == 8) r = fma(r, fma(-x, r, 1.0), r);
+  return r;
 }
 
 // exp(-E_a/(R T)): FP64 in FP64 mode; in FP32-bulk mode the rate only sets a
@@ -390,10 +407,10 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
     e = fma(sp[s].m, mb[3 * S + s][lane], e);
     kn = fma(sp[s].K, n, kn);
   }
-  const double irho = recip(rho);
+  const double irho = recip<T>(rho);
   cs.ux = px * irho;
   cs.uy = py * irho;
-  const double ikn = recip(kn);
+  const double ikn = recip<T>(kn);
   const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) * ikn;
   cs.Tst = Tm;
   cs.xi = 0.0;
@@ -403,7 +420,7 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
       if (s == I.fuel) nF = fmax(mb[0 * S + s][lane], 0.0);
       if (s == I.oxid) nO = fmax(mb[0 * S + s][lane], 0.0);
     }
-    double xi = I.k_ov * nF * nO * arrhenius<T>(-I.EaR * recip(Tm)) * sp[0].tau;
+    double xi = I.k_ov * nF * nO * arrhenius<T>(-I.EaR * recip<T>(Tm)) * sp[0].tau;
     double dkn = 0.0;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -411,7 +428,7 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
       dkn = fma(sp[s].K, sp[s].a, dkn);
     }
     // sum (D+I) n* = kn + xi sum (D+I) a
-    cs.Tst = fma(Tm, kn, I.Q2 * xi) * recip(fma(xi, dkn, kn));
+    cs.Tst = fma(Tm, kn, I.Q2 * xi) * recip<T>(fma(xi, dkn, kn));
     cs.xi = xi;
   }
 }
@@ -435,7 +452,7 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const
   const bool force = I.force && n > 1e-300;
   double fd[16];
   if (force) {
-    const double inv_n = recip(n);
+    const double inv_n = recip<T>(n);
     const double us = jx * inv_n, vs = jy * inv_n;
     const double Ts = sp.m * (E * inv_n - us * us - vs * vs) * sp.inv_K;
     double Td = Ts;
@@ -451,8 +468,10 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const
     d8 += fd[8];
     d12 += fd[12];
   }
-  const T DBM_CONST *MA = Tab<T>::MA(sp), *MB1 = Tab<T>::MB1(sp), *MB2 = Tab<T>::MB2(sp),
-                    *ME = Tab<T>::ME(sp);
+  const T DBM_CONST *MA = launder_after(Tab<T>::MA(sp), r[2]);
+  const T DBM_CONST *MB1 = launder_after(Tab<T>::MB1(sp), r[4]);
+  const T DBM_CONST *MB2 = launder_after(Tab<T>::MB2(sp), r[6]);
+  const T DBM_CONST *ME = launder_after(Tab<T>::ME(sp), r[9]);
   T d[16];
   d[0] = (T)d0;
   d[1] = (T)d1;
@@ -624,6 +643,35 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     const int rk = k * nx;
     SpC *sp = launder(as_const(I.sp));
     SpC &me = sp[s];
+    // Halo of the x-moving planes and the advection coefficients, fetched
+    // first so that their latency hides behind the moment exchange: h1 =
+    // f(x0-1) in lane 0 and f(x0+64) in lane 63; h2 = f(x0-2) (v_x > 0) or
+    // f(x0+65) (v_x < 0).
+    // (FP32 only: in FP64 the 24 extra doubles would not fit in registers,
+    // so there each plane gathers its halo where it is used.)
+    auto halo = [&](int j, T &a, T &b) {
+      if constexpr (kHaloGather<T>) {
+        a = bperm(hidx1 + 12 * j, hcur);
+        b = bperm(4 + 12 * j, hcur);
+      } else {
+        a = lane == 0 ? readlane(hcur, 3 * j) : readlane(hcur, 3 * j + 2);
+        b = readlane(hcur, 3 * j + 1);
+      }
+    };
+    constexpr bool kEarlyHalo = sizeof(T) == 4;
+    T h1[kXPlanes], h2[kXPlanes];
+    if constexpr (kEarlyHalo) {
+#pragma unroll
+      for (int j = 0; j < kXPlanes; ++j) halo(j, h1[j], h2[j]);
+    }
+    T cgx[4], cgy[4];
+    if constexpr (kEarlyHalo) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        cgx[g] = Tab<T>::cgx(me, g);
+        cgy[g] = Tab<T>::cgy(me, g);
+      }
+    }
     // Own species' FP64 moments to LDS; one barrier; everyone's back.
     T oA[4], oB[4], oX[4], oY[4];
     orbit_parts<T>(c, oA, oB, oX, oY);
@@ -647,6 +695,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, fma(me.a, cs.xi, n0), cs.ux,
                        cs.uy, cs.Tst, df);
     const T om = Tab<T>::omega(me);
+    T res[kNV];
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
       const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
@@ -655,33 +704,28 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
-      // Edge lanes take the tile's halo: h1 = f(x0-1) in lane 0 and
-      // f(x0+64) in lane 63; h2 = f(x0-2) (v_x > 0) or f(x0+65) (v_x < 0).
+      // The edge lanes take the tile's halo.
       if (sx != 0) {
         const int j = xplane_index(i);
-        T h1, h2;
-        if constexpr (kHaloGather<T>) {
-          h1 = bperm(hidx1 + 12 * j, hcur);
-          h2 = bperm(4 + 12 * j, hcur);
-        } else {
-          h1 = lane == 0 ? readlane(hcur, 3 * j) : readlane(hcur, 3 * j + 2);
-          h2 = readlane(hcur, 3 * j + 1);
-        }
-        const T dp = shl1e(f, h1) - f;               // f_{j+1} - f_j
-        const T dl = f - h1;                         // lane 0: f_{x0} - f_{x0-1}
+        if constexpr (!kEarlyHalo) halo(j, h1[j], h2[j]);
+        // Each edge operand is formed before its last use as a shift's
+        // `old` value, so the shifts can write in place.
+        const T dl = f - h1[j];                      // lane 0: f_{x0} - f_{x0-1}
+        const T e = sx > 0 ? h1[j] - h2[j] : h2[j] - h1[j];
+        const T dp = shl1e(f, h1[j]) - f;            // f_{j+1} - f_j
         T Dx;
         if (sx > 0) {
+          const T sle = slope_pos<LIM>(e, dl);       // lane 0: slope at x0-1
           const T d0 = shr1e(dp, dl);                // f_j - f_{j-1}
           const T sl = slope_pos<LIM>(d0, dp);       // limited slope at j
-          const T sle = slope_pos<LIM>(h1 - h2, dl);   // lane 0: slope at x0-1
           Dx = fma(T(0.5), sl - shr1e(sl, sle), d0);
         } else {
-          const T dhi = shl1e(dp, h2 - h1);          // lane 63: f_{x0+65} - f_{x0+64}
-          const T sl = slope_neg<LIM>(dp, dhi);      // limited slope at j+1
           const T sle = slope_neg<LIM>(dl, dp);      // lane 0: slope at x0
+          const T dhi = shl1e(dp, e);                // lane 63: f_{x0+65} - f_{x0+64}
+          const T sl = slope_neg<LIM>(dp, dhi);      // limited slope at j+1
           Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
         }
-        const T cx = Tab<T>::cgx(me, g);
+        const T cx = kEarlyHalo ? cgx[g] : Tab<T>::cgx(me, g);
         acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
       }
       // y: NND difference from the carried rows; advance the state.
@@ -690,7 +734,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T dn = fnew - f;
         const T sk = slope_pos<LIM>(y1[i], dn);
         const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
-        acc = fma(-Tab<T>::cgy(me, g), Dy, acc);
+        acc = fma(-(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g)), Dy, acc);
         c[i] = fnew;
         y1[i] = dn;
         y2[i] = sk;
@@ -699,18 +743,28 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T dlo = n1 - f, dhi = fnew - n1;
         const T tk1 = slope_neg<LIM>(dlo, dhi);
         const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
-        acc = fma(Tab<T>::cgy(me, g), Dy, acc);
+        acc = fma(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g), Dy, acc);
         c[i] = n1;
         y1[i] = fnew;
         y2[i] = tk1;
       } else {
         c[i] = fnew;
       }
-      T res = fma(om, df[i], acc);
+      res[i] = fma(om, df[i], acc);
       // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
       // the (small) stage difference
-      if constexpr (RKC) res = fma(alpha, fnv[i] - res, res);
-      if (writer) bstore(rout, res, (uint32_t)(rk + col) * es, i * plb);
+      if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
+      if constexpr (!kEarlyHalo)
+        if (writer) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+    }
+    // FP32: one masked block of stores per row (lanes past nx hold wrapped
+    // or clamped copies and write nothing), so that the row is one basic
+    // block for the scheduler.
+    if constexpr (kEarlyHalo) {
+      if (writer) {
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+      }
     }
   };
 
