@@ -159,6 +159,16 @@ int dbm_get_option(dbm_handle h, int option, int *value);
  * The simulation state is not changed.  Synchronises. */
 int dbm_time_stage_kernel(dbm_handle h, int reps, double *ms_per_launch);
 
+/* Measurement reference, not part of the method: copies `bytes` (a multiple
+ * of 16, both pointers device memory aligned to 16 bytes, not overlapping)
+ * from src to dst with a grid-stride streaming copy of 16-byte words on
+ * `grid` workgroups of 256 threads, `reps` times after one warm-up copy, on
+ * hip_stream (NULL = default stream), and returns the mean duration of one
+ * copy in milliseconds from HIP events.  The achievable HBM rate is then
+ * 2 bytes / time.  Synchronises; DBM_ERR_ARG on bad arguments. */
+int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
+                  void *hip_stream, double *ms_per_copy);
+
 /* Thread-local description of the last error. */
 const char *dbm_last_error(void);
 

@@ -39,6 +39,7 @@ hipError_t launch_check(bool fp32, const InstDev *insts, int inst, size_t cells,
                         int *flag, hipStream_t st);
 hipError_t launch_dpp_probe(int *out, hipStream_t st);
 hipError_t launch_delay(double microseconds, hipStream_t st);
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipStream_t st);
 }  // namespace dbm
 
 using namespace dbm;
@@ -733,6 +734,31 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_PERSISTENT: *value = h->resident; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
+  return DBM_OK;
+}
+
+int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
+                  void *hip_stream, double *ms_per_copy) {
+  if (!src || !dst || !ms_per_copy || reps < 1 || grid < 1 || bytes < 16 || bytes % 16 ||
+      ((uintptr_t)src | (uintptr_t)dst) % 16)
+    return fail(DBM_ERR_ARG, "dbm_copy_rate: bad arguments");
+  const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+  if (a < b + bytes && b < a + bytes) return fail(DBM_ERR_ARG, "dbm_copy_rate: buffers overlap");
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) e = launch_copy16(src, dst, bytes / 16, grid, st);  // warm-up
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy16(src, dst, bytes / 16, grid, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(DBM_ERR_HIP, std::string("dbm_copy_rate: ") + hipGetErrorString(e));
+  *ms_per_copy = ms / reps;
   return DBM_OK;
 }
 

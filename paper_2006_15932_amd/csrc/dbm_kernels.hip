@@ -1416,6 +1416,23 @@ hipError_t launch_check(bool fp32, const InstDev *insts, int inst, size_t cells,
   return hipGetLastError();
 }
 
+// Streaming copy of n16 16-byte words (grid-stride, non-temporal stores):
+// the achievable-bandwidth reference the stage kernel is compared with.
+__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
+                                                uint4 *__restrict__ dst, size_t n16) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4 *a = (const u32x4 *)src;
+  u32x4 *b = (u32x4 *)dst;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
+    __builtin_nontemporal_store(a[i], &b[i]);
+}
+
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst,
+                     n16);
+  return hipGetLastError();
+}
+
 hipError_t launch_delay(double microseconds, hipStream_t st) {
   int dev = 0, khz = 0;
   hipError_t e = hipGetDevice(&dev);

@@ -75,6 +75,8 @@ SIGNATURES = {
     "dbm_set_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "dbm_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "dbm_time_stage_kernel": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
+    "dbm_copy_rate": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _vp,
+                                     _dp]),
     "dbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -200,6 +202,26 @@ def dbm_time_stage_kernel(h, reps) -> float:
     ms = ctypes.c_double(0.0)
     _check(lib().dbm_time_stage_kernel(_vp(h), int(reps), ctypes.byref(ms)))
     return ms.value
+
+
+def dbm_copy_rate(src_ptr, dst_ptr, nbytes, grid, reps, stream_ptr) -> float:
+    """Mean milliseconds of one device-to-device streaming copy of nbytes."""
+    ms = ctypes.c_double(0.0)
+    _check(lib().dbm_copy_rate(_vp(src_ptr), _vp(dst_ptr), ctypes.c_size_t(nbytes), int(grid),
+                               int(reps), _vp(stream_ptr), ctypes.byref(ms)))
+    return ms.value
+
+
+def copy_rate_gbs(nbytes=1 << 30, grid=1024, reps=10, device="cuda:0") -> float:
+    """Achievable HBM rate (read + write GB/s) of the library's streaming copy
+    on two fresh buffers of nbytes each."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream(device)
+    ms = dbm_copy_rate(a.data_ptr(), b.data_ptr(), nbytes, grid, reps, st.cuda_stream)
+    del a, b
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
 class Simulation:

@@ -51,6 +51,8 @@ def field_errors(p, mom_gpu, mom_or):
     # reported against max(max|u|, 0.01 c_s) ("u_strict").
     out["u"] = du / max(umax, cs)
     out["u_strict"] = du / max(umax, 0.01 * cs)
+    out["ux"] = np.abs(uxg - uxo).max() / max(umax, cs)
+    out["uy"] = np.abs(uyg - uyo).max() / max(umax, cs)
     out["T"] = np.abs(Tg - To).max() / np.abs(To).max()
     return out
 

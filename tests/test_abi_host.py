@@ -113,3 +113,20 @@ def test_null_handle_calls_fail_cleanly():
     assert L.dbm_step(None, 1) == D.DBM_ERR_ARG
     assert L.dbm_destroy(None) == D.DBM_ERR_ARG
     assert L.dbm_moments(None, 0, None, None, None, None) == D.DBM_ERR_ARG
+
+
+@pytest.mark.parametrize("src,dst,nbytes,grid,reps", [
+    (0, 1 << 20, 4096, 64, 1),            # null source
+    (1 << 20, 0, 4096, 64, 1),            # null destination
+    (1 << 20, 1 << 24, 4100, 64, 1),      # not a multiple of 16 bytes
+    (1 << 20, 1 << 24, 0, 64, 1),         # empty
+    (1 << 20, (1 << 20) + 8, 4096, 64, 1),  # misaligned and overlapping
+    (1 << 20, (1 << 20) + 1024, 4096, 64, 1),  # overlapping
+    (1 << 20, 1 << 24, 4096, 0, 1),       # no workgroups
+    (1 << 20, 1 << 24, 4096, 64, 0),      # no repetitions
+])
+def test_copy_rate_rejects_bad_arguments_before_any_launch(src, dst, nbytes, grid, reps):
+    # the addresses are never dereferenced: validation happens on the host
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_copy_rate(src, dst, nbytes, grid, reps, 0)
+    assert e.value.code == D.DBM_ERR_ARG

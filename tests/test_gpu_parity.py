@@ -235,3 +235,16 @@ def test_stage_kernel_timer_leaves_state_unchanged():
     ms = sim.time_stage_kernel(5)
     assert ms > 0
     np.testing.assert_array_equal(f, sim.get_f())
+
+
+def test_copy_rate_reference_copies_and_times():
+    """The measurement reference copy moves the bytes it claims to."""
+    import torch
+    n = 1 << 22
+    a = torch.arange(n // 4, dtype=torch.int32, device="cuda")
+    b = torch.zeros_like(a)
+    st = torch.cuda.current_stream()
+    ms = D.dbm_copy_rate(a.data_ptr(), b.data_ptr(), n, 256, 3, st.cuda_stream)
+    torch.cuda.synchronize()
+    assert ms > 0
+    assert torch.equal(a, b)
