@@ -139,6 +139,19 @@ int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, 
  * in a fixed order (may be NULL).  Synchronises. */
 int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals);
 
+/* Translational energies and energy fluxes defined with the nonequilibrium
+ * measures (the paragraph after Eqs.(21)-(23)), per species, with
+ * M2aa(g) = m sum_i g_i v_ia^2 and M31a(g) = m sum_i g_i (v_i^2 + eta_i^2) v_ia
+ * and f^eq = f^eq(n^s, u, T): fields [S][8][ny][nx] in the order
+ *   1/2 M2xx(f), 1/2 M2yy(f)        translational energy in x, y
+ *   1/2 M2xx(f^eq), 1/2 M2yy(f^eq)  its equilibrium part
+ *   1/2 M31x(f), 1/2 M31y(f)        total energy flux in x, y
+ *   1/2 M31x(f^eq), 1/2 M31y(f^eq)  organised energy flux
+ * (the nonorganised energy and flux are the differences, i.e. 1/2 Delta_2aa
+ * and 1/2 Delta_3,1a), and FP64 domain totals [S][8] (times dx dy, reduced in
+ * a fixed order).  Either pointer may be NULL.  Synchronises. */
+int dbm_energy_moments(dbm_handle h, int inst, double *fields, double *totals);
+
 /* Options (dbm_set_option / dbm_get_option). */
 enum {
   DBM_OPT_PATH = 1,         /* 0 fused one-pass kernels (default), 1 plain    */

@@ -578,3 +578,52 @@ int or_noneq(const or_model *md, const double *f, double *delta, double *totals)
   }
   return 0;
 }
+
+/* Energies and energy fluxes of the paragraph after Eqs.(21)-(23): sums over
+ * the 16 discrete velocities of m f_i times v_ix^2, v_iy^2, q_i v_ix, q_i v_iy
+ * (halved), for f and for f^eq(n^s, u, T) = M^{-1} fhat. */
+static void energy_cell(const or_model *md, int s, const double *g, double *out4) {
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int i = 0; i < NV; ++i) {
+    const double vx = md->vx[s][i], vy = md->vy[s][i], q = md->q[s][i];
+    a += g[i] * vx * vx;
+    b += g[i] * vy * vy;
+    c += g[i] * q * vx;
+    d += g[i] * q * vy;
+  }
+  const double hm = 0.5 * md->sp[s].m;
+  out4[0] = hm * a; out4[1] = hm * b; out4[2] = hm * c; out4[3] = hm * d;
+}
+
+int or_energy(const or_model *md, const double *f, double *fields, double *totals) {
+  if (!md || !f) return -1;
+  const or_config *c = &md->cfg;
+  const int S = c->S;
+  const size_t plane = (size_t)c->nx * c->ny;
+  if (totals)
+    for (int k = 0; k < 8 * S; ++k) totals[k] = 0.0;
+  /* cells in order, so that the totals are summed in a fixed order */
+  for (size_t cell = 0; cell < plane; ++cell) {
+    double fc[OR_MAXS][NV], n[OR_MAXS], jx[OR_MAXS], jy[OR_MAXS], E[OR_MAXS];
+    for (int s = 0; s < S; ++s) {
+      for (int i = 0; i < NV; ++i) fc[s][i] = f[((size_t)s * NV + i) * plane + cell];
+      species_moments(md, s, fc[s], &n[s], &jx[s], &jy[s], &E[s]);
+    }
+    double rho, u, v, t;
+    mixture(md, n, jx, jy, E, &rho, &u, &v, &t);
+    for (int s = 0; s < S; ++s) {
+      double feq[NV], ef[4], ee[4];
+      or_feq(md, s, n[s], u, v, t, feq);
+      energy_cell(md, s, fc[s], ef);
+      energy_cell(md, s, feq, ee);
+      const double vals[8] = {ef[0], ef[1], ee[0], ee[1], ef[2], ef[3], ee[2], ee[3]};
+      for (int k = 0; k < 8; ++k) {
+        if (fields) fields[((size_t)s * 8 + k) * plane + cell] = vals[k];
+        if (totals) totals[s * 8 + k] += vals[k];
+      }
+    }
+  }
+  if (totals)
+    for (int k = 0; k < 8 * S; ++k) totals[k] *= c->dx * c->dy;
+  return 0;
+}

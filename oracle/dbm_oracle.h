@@ -95,6 +95,13 @@ int or_moments(const or_model *md, const double *f, double *rho_sp, double *ux,
  * NULL) and domain totals [S+3] = mass^sigma, Px, Py, E. */
 int or_noneq(const or_model *md, const double *f, double *delta, double *totals);
 
+/* Translational energies and energy fluxes defined after Eqs.(21)-(23), per
+ * species and cell (8 per species, may be NULL): 1/2 m sum f v_x^2,
+ * 1/2 m sum f v_y^2, the same over f^eq(n^s, u, T), 1/2 m sum f q v_x,
+ * 1/2 m sum f q v_y, the same over f^eq (q = v^2 + eta^2); totals [S][8] are
+ * their domain integrals (may be NULL). */
+int or_energy(const or_model *md, const double *f, double *fields, double *totals);
+
 #ifdef __cplusplus
 }
 #endif

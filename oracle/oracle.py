@@ -78,6 +78,7 @@ def lib():
         L.or_run.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int]
         L.or_moments.argtypes = [ctypes.c_void_p] + [_dp] * 5
         L.or_noneq.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
+        L.or_energy.argtypes = [ctypes.c_void_p, _dp, _dp, _dp]
         _lib = L
     return _lib
 
@@ -206,6 +207,15 @@ class Oracle:
         totals = np.zeros(self.S + 3)
         self._check(lib().or_noneq(self._h, _ptr(f), _ptr(delta), _ptr(totals)))
         return delta, totals
+
+    def energy(self, f, want_fields=True):
+        """Energies and energy fluxes [S][8] per cell and their totals."""
+        p = self.prob
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        fields = np.zeros((self.S, 8, p.ny, p.nx)) if want_fields else None
+        totals = np.zeros((self.S, 8))
+        self._check(lib().or_energy(self._h, _ptr(f), _ptr(fields), _ptr(totals)))
+        return fields, totals
 
     @staticmethod
     def _check(rc):

@@ -31,6 +31,11 @@ hipError_t launch_moments(bool fp32, const InstDev *insts, int inst, size_t cell
 hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int which, double *dst, hipStream_t st);
 int totals_blocks();
+int energy_rows();
+hipError_t launch_energy(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+                         int which, double *dst, hipStream_t st);
+hipError_t launch_rowsums(const double *src, int nrows, size_t cells, double area, double *part,
+                          double *out, hipStream_t st);
 hipError_t launch_totals(bool fp32, const InstDev *insts, int inst, int in_idx, int nq,
                          double area, double *partials, double *out, hipStream_t st);
 hipError_t launch_widen(bool fp32, const void *src, double *dst, size_t n, hipStream_t st);
@@ -139,10 +144,13 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   for (int k = 0; k < ninst; ++k) L.tile_cap += (size_t)tiles_x(cfgs[k].nx) * cfgs[k].ny;
   L.tile_off = off;
   off = align_up(off + sizeof(Tile) * L.tile_cap);
+  // per-block partials and totals of the mass/momentum/energy sums (S + 3
+  // values) and of the energy diagnostics (energy_rows() per species)
+  const size_t nq = std::max<size_t>(S + 3, energy_rows());
   L.part_off = off;
-  off = align_up(off + sizeof(double) * (size_t)totals_blocks() * (S + 3));
+  off = align_up(off + sizeof(double) * (size_t)totals_blocks() * nq);
   L.tot_off = off;
-  off = align_up(off + sizeof(double) * (S + 3));
+  off = align_up(off + sizeof(double) * std::max<size_t>(S + 3, (size_t)energy_rows() * S));
   L.flag_off = off;
   off = align_up(off + sizeof(int));
   L.probe_off = off;
@@ -683,6 +691,28 @@ int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals) {
                          h->cfg[inst].dx * h->cfg[inst].dy, part, tot, h->stream));
     HIPCHK(hipMemcpyAsync(totals, tot, sizeof(double) * nq, hipMemcpyDeviceToHost, h->stream));
   }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_energy_moments(dbm_handle h, int inst, double *fields, double *totals) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  const size_t cells = h->cells(inst);
+  const int nr = energy_rows();
+  double *stage = (double *)h->inst[inst].scratch;
+  double *part = (double *)(h->ws + h->L.part_off), *tot = (double *)(h->ws + h->L.tot_off);
+  const double area = h->cfg[inst].dx * h->cfg[inst].dy;
+  for (int s = 0; s < h->S; ++s) {
+    HIPCHK(launch_energy(h->fp32, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
+    if (fields)
+      HIPCHK(hipMemcpyAsync(fields + (size_t)s * nr * cells, stage, sizeof(double) * nr * cells,
+                            hipMemcpyDeviceToHost, h->stream));
+    if (totals) HIPCHK(launch_rowsums(stage, nr, cells, area, part, tot + (size_t)s * nr, h->stream));
+  }
+  if (totals)
+    HIPCHK(hipMemcpyAsync(totals, tot, sizeof(double) * nr * h->S, hipMemcpyDeviceToHost,
+                          h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DBM_OK;
 }

@@ -1121,6 +1121,59 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 constexpr int kTotBlocks = 512;
+// Translational energies and energy fluxes of species `which` (the
+// nonequilibrium measures section of the paper), 8 FP64 fields per cell:
+//   1/2 M2xx(f), 1/2 M2yy(f), 1/2 M2xx(f^eq), 1/2 M2yy(f^eq),
+//   1/2 M31x(f), 1/2 M31y(f), 1/2 M31x(f^eq), 1/2 M31y(f^eq),
+// with M2aa(g) = m sum_i g_i v_ia^2 and M31a(g) = m sum_i g_i (v_i^2 + eta_i^2)
+// v_ia; f^eq = f^eq(n^s, u, T) as for Delta.  Moments of f come from rows
+// v_x^2, v_y^2, q v_x, q v_y of M; those of f^eq are the closed forms of
+// fhat (M M^{-1} fhat = fhat).
+template <typename T>
+__global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ insts, int inst,
+                                                int in_idx, int which,
+                                                double *__restrict__ dst) {
+  const InstDev &I = insts[inst];
+  const size_t plane = (size_t)I.nx * I.ny;
+  const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= plane) return;
+  const T *f = (const T *)I.buf[in_idx];
+  double rho = 0, px = 0, py = 0, e = 0, kn = 0, nw = 0;
+  for (int s = 0; s < I.S; ++s) {
+    double n, jx, jy, E;
+    dense_moments<T>(I, f, plane, cell, s, n, jx, jy, E);
+    const double m = I.sp[s].m;
+    if (s == which) nw = n;
+    rho = fma(m, n, rho);
+    px = fma(m, jx, px);
+    py = fma(m, jy, py);
+    e = fma(m, E, e);
+    kn = fma(I.sp[s].K, n, kn);
+  }
+  const double ux = px / rho, uy = py / rho;
+  const double Tm = (e - rho * (ux * ux + uy * uy)) / kn;
+  const SpeciesDev &sp = I.sp[which];
+  const double th = Tm * sp.inv_m, u2 = ux * ux + uy * uy;
+  const double e2 = (sp.K + 2.0) * th + u2;
+  constexpr int rows[4] = {4, 6, 7, 8};  // v_x^2, v_y^2, q v_x, q v_y
+  double mf[4];
+  for (int r = 0; r < 4; ++r) {
+    double acc = 0.0;
+    for (int i = 0; i < kNV; ++i)
+      acc = fma(sp.M[rows[r] * kNV + i], (double)f[(size_t)(which * kNV + i) * plane + cell], acc);
+    mf[r] = acc;
+  }
+  const double hm = 0.5 * sp.m;
+  dst[0 * plane + cell] = hm * mf[0];
+  dst[1 * plane + cell] = hm * mf[1];
+  dst[2 * plane + cell] = hm * nw * (th + ux * ux);
+  dst[3 * plane + cell] = hm * nw * (th + uy * uy);
+  dst[4 * plane + cell] = hm * mf[2];
+  dst[5 * plane + cell] = hm * mf[3];
+  dst[6 * plane + cell] = hm * nw * ux * e2;
+  dst[7 * plane + cell] = hm * nw * uy * e2;
+}
+
 constexpr int kTotThreads = 256;
 
 // Partial totals per block: [block][S+3] = mass^s, Px, Py, E (unscaled).
@@ -1157,6 +1210,31 @@ __global__ __launch_bounds__(kTotThreads) void k_totals_partial(const InstDev *_
     double s = 0.0;
     for (int k = 0; k < kTotThreads / kWave; ++k) s += red[k][threadIdx.x];
     part[(size_t)blockIdx.x * nq + threadIdx.x] = s;
+  }
+}
+
+// Deterministic per-block sums of nrows (<= kEnergyRows) FP64 fields of
+// `cells` values each (fixed grid, fixed order), finished by k_totals_final.
+constexpr int kEnergyRows = 8;
+__global__ __launch_bounds__(kTotThreads) void k_rows_partial(const double *__restrict__ src,
+                                                              int nrows, size_t cells,
+                                                              double *__restrict__ part) {
+  double acc[kEnergyRows];
+  for (int r = 0; r < kEnergyRows; ++r) acc[r] = 0.0;
+  for (size_t c = (size_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells;
+       c += (size_t)gridDim.x * blockDim.x)
+    for (int r = 0; r < nrows; ++r) acc[r] += src[(size_t)r * cells + c];
+  __shared__ double red[kTotThreads / kWave][kEnergyRows];
+  const int w = threadIdx.x / kWave, l = threadIdx.x % kWave;
+  for (int r = 0; r < nrows; ++r) {
+    const double v = wave_sum(acc[r]);
+    if (l == 0) red[w][r] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < nrows) {
+    double s = 0.0;
+    for (int k = 0; k < kTotThreads / kWave; ++k) s += red[k][threadIdx.x];
+    part[(size_t)blockIdx.x * nrows + threadIdx.x] = s;
   }
 }
 
@@ -1371,6 +1449,28 @@ hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells,
 }
 
 int totals_blocks() { return kTotBlocks; }
+int energy_rows() { return kEnergyRows; }
+
+hipError_t launch_energy(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+                         int which, double *dst, hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(k_energy<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+                       inst, in_idx, which, dst);
+  else
+    hipLaunchKernelGGL(k_energy<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+                       inst, in_idx, which, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowsums(const double *src, int nrows, size_t cells, double area, double *part,
+                          double *out, hipStream_t st) {
+  if (nrows < 1 || nrows > kEnergyRows) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_rows_partial, dim3(kTotBlocks), dim3(kTotThreads), 0, st, src, nrows,
+                     cells, part);
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, (const double *)part, kTotBlocks,
+                     nrows, area, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_totals(bool fp32, const InstDev *insts, int inst, int in_idx, int nq,
                          double area, double *partials, double *out, hipStream_t st) {

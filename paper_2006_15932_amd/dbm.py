@@ -74,6 +74,7 @@ SIGNATURES = {
     "dbm_noneq_moments": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "dbm_set_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int]),
     "dbm_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "dbm_energy_moments": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "dbm_time_stage_kernel": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "dbm_copy_rate": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _vp,
                                      _dp]),
@@ -188,6 +189,13 @@ def dbm_noneq_moments(h, inst, S, ny, nx, want_delta=True):
     return delta, totals
 
 
+def dbm_energy_moments(h, inst, S, ny, nx, want_fields=True):
+    fields = np.zeros((S, 8, ny, nx)) if want_fields else None
+    totals = np.zeros((S, 8))
+    _check(lib().dbm_energy_moments(_vp(h), inst, _dptr(fields), _dptr(totals)))
+    return fields, totals
+
+
 def dbm_set_option(h, option, value) -> None:
     _check(lib().dbm_set_option(_vp(h), option, int(value)))
 
@@ -284,6 +292,10 @@ class Simulation:
     def noneq(self, inst=0, want_delta=True):
         p = self._p(inst)
         return dbm_noneq_moments(self.h, inst, p.S, p.ny, p.nx, want_delta)
+
+    def energy(self, inst=0, want_fields=True):
+        p = self._p(inst)
+        return dbm_energy_moments(self.h, inst, p.S, p.ny, p.nx, want_fields)
 
     def set_option(self, option, value):
         dbm_set_option(self.h, option, value)

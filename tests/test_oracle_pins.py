@@ -504,3 +504,104 @@ def test_create_rejects_bad_input():
     with pytest.raises(O.OracleError) as e:
         O.Oracle(_prob([good]).with_(nx=0))
     assert e.value.code == -1
+
+
+# ---------------------------------------------------------------------------
+# Energies and energy fluxes (the paragraph after Eqs.(21)-(23)).
+# ---------------------------------------------------------------------------
+def test_energy_of_equilibrium_matches_maxwellian_closed_forms():
+    """For f = f^eq the translational energy in direction a is
+    1/2 rho (T/m + u_a^2) and the organised energy flux is
+    1/2 rho u_a ((D+I+2) T/m + u^2): moments of the Maxwellian of Eq.(7),
+    here by quadrature; f and f^eq parts coincide."""
+    sp = _three_species()
+    n_sp, ux, uy, T = [0.05, 0.03, 0.02], 0.4, -0.3, 1.3
+    p = _uniform(W.Problem("eq", 5, 3, sp), n_sp, ux, uy, T)
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    fields, tot = o.energy(f)
+    for s, spc in enumerate(sp):
+        mom = maxwellian_moments(n_sp[s], ux, uy, T, spc.m, spc.I)
+        m = spc.m
+        want = 0.5 * m * np.array([mom[4], mom[6], mom[4], mom[6], mom[7], mom[8], mom[7], mom[8]])
+        got = fields[s][:, 0, 0]
+        np.testing.assert_allclose(got, want, rtol=1e-10)
+        # closed forms written out
+        K = 2 + spc.I
+        rho = m * n_sp[s]
+        np.testing.assert_allclose(got[2], 0.5 * rho * (T / m + ux * ux), rtol=1e-12)
+        np.testing.assert_allclose(got[6], 0.5 * rho * ux * ((K + 2) * T / m + ux * ux + uy * uy),
+                                   rtol=1e-12)
+        np.testing.assert_allclose(tot[s], fields[s].sum(axis=(1, 2)) * 1e-6, rtol=1e-13)
+
+
+def test_energy_of_single_velocity_by_brute_force():
+    """One particle population on one discrete velocity: the energies of f
+    are 1/2 m v_a^2 and 1/2 m (v^2 + eta^2) v_a of that velocity (Eq.15)."""
+    sp = W.Species(m=3.0, v=(1.1, 0.7, 2.3, 1.9), eta=(0.4, 0.6, 0.8, 1.0))
+    o = O.Oracle(_prob([sp], nx=1, ny=1))
+    for i in range(16):
+        g, j = divmod(i, 4)
+        axis = [(1, 0), (0, 1), (-1, 0), (0, -1)]
+        diag = [(1, 1), (-1, 1), (-1, -1), (1, -1)]
+        dx, dy = (axis if g % 2 == 0 else diag)[j]
+        vx, vy, eta = sp.v[g] * dx, sp.v[g] * dy, sp.eta[g]
+        f = np.zeros((1, 16, 1, 1))
+        f[0, i] = 0.25
+        fields, _ = o.energy(f)
+        q = vx * vx + vy * vy + eta * eta
+        got = fields[0][[0, 1, 4, 5], 0, 0]
+        want = 0.5 * 3.0 * 0.25 * np.array([vx * vx, vy * vy, q * vx, q * vy])
+        np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-15)
+
+
+def test_nonorganised_energy_and_flux_are_half_delta():
+    """1/2 Delta_2aa = 1/2 M2aa(f) - 1/2 M2aa(f^eq) and 1/2 Delta_3,1a =
+    1/2 M31a(f) - 1/2 M31a(f^eq): the energy route (sums over velocities)
+    against the Delta route (rows of M)."""
+    sp = _three_species()
+    p = _uniform(W.Problem("neq", 4, 3, sp), [0.05, 0.03, 0.02], 0.2, 0.1, 1.1)
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    r = W.splitmix64(99, f.size).reshape(f.shape)
+    f = f * (1 + 0.05 * (2 * r - 1))
+    fields, _ = o.energy(f)
+    delta, _ = o.noneq(f)
+    for s in range(3):
+        scale = np.abs(fields[s]).max()
+        for a, b, d in ((0, 2, 0), (1, 3, 2), (4, 6, 3), (5, 7, 4)):
+            np.testing.assert_allclose(fields[s][a] - fields[s][b], 0.5 * delta[s, d],
+                                       rtol=0, atol=1e-12 * scale)
+
+
+def test_heat_flux_matches_chapman_enskog():
+    """The nonorganised energy flux 1/2 Delta_3,1 against the Chapman-Enskog
+    form under Eqs.(21)-(23): at rest with one species it is
+    -kappa d/dx((D+I)/2 T/m), kappa = gamma mu, mu = p tau (Fourier's law with
+    c_p mu), for a small temperature wave at uniform pressure.  Eq.(19) has no
+    factor 1/2, and the text after the NS equations names 1/2 Delta_3,1 the
+    nonorganised energy flux; the closed form holds for that half."""
+    tau, dt, nx = 5e-4, 5e-6, 64
+    m, I = 1.0, 3.0
+    sp = [W.make_species(m, I=I, tau=tau)]
+    xc = (np.arange(nx) + 0.5) * 1e-3
+    k = 2 * math.pi / (nx * 1e-3)
+    eps = 2e-3
+    T0 = 1.0 + eps * np.sin(k * xc)
+    p = W.Problem("heat", nx, 1, sp, dt=dt, limiter=W.LIM_NONE,
+                  n_sp=(1.0 / T0)[None, None, :], ux=np.zeros((1, nx)), uy=np.zeros((1, nx)),
+                  T=T0[None, :])
+    o = O.Oracle(p)
+    f = o.run(o.init_equilibrium(*W.fields(p)), 2000)    # 20 tau: the closure forms
+    delta, _ = o.noneq(f)
+    rho, _, _, T = o.moments(f)
+    T = T[0]
+    amp = 2.0 * np.mean((T - T.mean()) * np.sin(k * xc))
+    ph = 2.0 * np.mean((T - T.mean()) * np.cos(k * xc))
+    dTdx = k * (amp * np.cos(k * xc) - ph * np.sin(k * xc))
+    K = 2 + I
+    pres = (rho[0] / m) * T
+    kappa = (K + 2) / K * pres * tau
+    ce = -kappa * (K / 2) * dTdx / m
+    err = np.abs(0.5 * delta[0, 3, 0] - ce).max() / np.abs(ce).max()
+    assert err < 0.02, err
