@@ -1,0 +1,78 @@
+"""One-dimensional validations of the oracle in invariant form (the paper's
+shock, reacting-wave and free-falling-box tests with synthetic parameters):
+a normal shock built from the Rankine-Hugoniot relations stays where it is,
+and the energy released by the reaction and the work of the force are
+accounted for exactly."""
+import numpy as np
+
+import validation_cases as V
+from oracle import oracle as O
+from paper_2006_15932_amd import workloads as W
+
+
+def test_rankine_hugoniot_shock_is_stationary():
+    p, st = V.stationary_shock()
+    O.set_threads(8)
+    o = O.Oracle(p)
+    f = o.run(o.init_equilibrium(*W.fields(p)), 500)     # the shock forms its structure
+    rho, ux, _, T = o.moments(f)
+    x500 = V.shock_position(rho.sum(0)[0], st["rho1"], st["rho2"])
+    g = o.run(f, 1500)
+    rho, ux, _, T = o.moments(g)
+    r = rho.sum(0)[0]
+    x2000 = V.shock_position(r, st["rho1"], st["rho2"])
+    assert abs(x500 - st["x_shock"]) < 1.0
+    assert abs(x2000 - x500) < 0.2, (x500, x2000)
+    # both plateaus keep their Rankine-Hugoniot states
+    for j, side in ((100, "1"), (300, "2")):
+        assert abs(r[j] / st["rho" + side] - 1) < 1e-9
+        assert abs(ux[0, j] / st["u" + side] - 1) < 1e-9
+        assert abs(T[0, j] / st["T" + side] - 1) < 1e-9
+
+
+def _fuel_count(o, p, f):
+    rho = o.moments(f)[0]
+    return rho[0].sum() / p.species[0].m * p.dx * p.dy
+
+
+def test_reacting_wave_energy_release_is_exact():
+    """Periodic premix with heat release Q: total energy grows by exactly Q
+    per unit extent, i.e. Q/2 per fuel particle consumed (a_F = -2); mass and
+    momentum are conserved."""
+    p = V.reacting_wave()
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    _, t0 = o.noneq(f, want_delta=False)
+    nf0 = _fuel_count(o, p, f)
+    g = o.run(f, p.steps)
+    _, t1 = o.noneq(g, want_delta=False)
+    release = p.reaction["Q"] * (nf0 - _fuel_count(o, p, g)) / 2
+    assert release > 1e-3 * (t1[-1] - t0[-1]) > 0           # the reaction did run
+    assert abs((t1[-1] - t0[-1]) - release) <= 1e-11 * t0[-1]
+    assert abs(t1[:3].sum() - t0[:3].sum()) <= 1e-12 * t0[:3].sum()
+    assert np.abs(t1[3:5]).max() <= 1e-12 * t0[:3].sum()
+
+
+def test_free_falling_reacting_box_energy_budget():
+    """Uniform reacting box under a force (the paper's first test, with
+    synthetic chemistry): u = a t exactly, and after n forward-Euler steps the
+    total energy has grown by the chemical release plus the work of the force,
+    M |a|^2 dt^2 n (n-1) / 2."""
+    p = V.free_falling_reacting_box()
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    _, t0 = o.noneq(f, want_delta=False)
+    nf0 = _fuel_count(o, p, f)
+    n = p.steps
+    g = o.run(f, n)
+    _, t1 = o.noneq(g, want_delta=False)
+    _, ux, uy, _ = o.moments(g)
+    t = n * p.dt
+    np.testing.assert_allclose([ux.mean(), uy.mean()], np.array(p.accel) * t, rtol=1e-9)
+    M = t0[:3].sum()
+    np.testing.assert_allclose(t1[3:5], M * np.array(p.accel) * t, rtol=1e-9)
+    a2 = p.accel[0] ** 2 + p.accel[1] ** 2
+    work = 0.5 * M * a2 * p.dt ** 2 * n * (n - 1)
+    release = p.reaction["Q"] * (nf0 - _fuel_count(o, p, g)) / 2
+    assert abs((t1[-1] - t0[-1]) - release - work) <= 1e-12 * t0[-1]
+    assert work > 1e-4 * release
