@@ -75,6 +75,21 @@ typedef struct {
   double k_ov, Ea_over_R, Q;
 } dbm_reaction;
 
+/* One step of a multi-step mechanism (the text after Eqs.(1)-(2) allows
+ * detailed or reduced multi-step kinetics): the rate law of Eq.(2) with its
+ * own reactant pair and constants, heat Q per unit extent, and its own
+ * stoichiometric coefficients a[s] (< 0 reactant, > 0 product) for species
+ * 0 .. nspecies-1 (entries beyond nspecies are ignored).  fuel and oxidiser
+ * may be the same species (rate k n^2 exp(-Ea/RT)).  With several steps,
+ * n^s* = n^s + sum_r a_r^s xi_r, xi_r = omega_r tau, and one common factor
+ * scales every xi_r when a reactant would otherwise be overdrawn. */
+#define DBM_MAX_REACTION_STEPS 4
+typedef struct {
+  int fuel, oxidiser;
+  double k_ov, Ea_over_R, Q;
+  double a[16];
+} dbm_reaction_step;
+
 /* One simulation instance. */
 typedef struct {
   int nx, ny;                    /* grid size, >= 1                           */
@@ -88,6 +103,9 @@ typedef struct {
   int time_scheme;               /* DBM_EULER | DBM_TVD_RK3                   */
   int limiter;                   /* DBM_LIM_MINMOD | DBM_LIM_NONE             */
   int force_T_mode;              /* temperature T_dagger of Eq.(6)            */
+  int nchem;                     /* 0 .. DBM_MAX_REACTION_STEPS; > 0: the     */
+  const dbm_reaction_step *chem; /* mechanism replaces `reaction` and the    */
+                                 /* species' a_stoich                         */
 } dbm_config;
 
 typedef struct dbm_s *dbm_handle;

@@ -44,6 +44,7 @@
 struct or_model {
   or_config cfg;
   or_species sp[OR_MAXS];
+  or_reaction_step chem[OR_MAXR];
   double vx[OR_MAXS][NV], vy[OR_MAXS][NV], eta[OR_MAXS][NV], q[OR_MAXS][NV];
   double M[OR_MAXS][NV * NV], Minv[OR_MAXS][NV * NV];
   int mirx[OR_MAXS][NV], miry[OR_MAXS][NV];
@@ -179,11 +180,22 @@ int or_create(const or_config *cfg, or_model **out) {
     for (int s = 1; s < c->S; ++s)
       if (c->sp[s].tau != c->sp[0].tau) return -5;
   }
+  if (c->nchem < 0 || c->nchem > OR_MAXR || (c->nchem > 0 && !c->chem)) return -1;
+  for (int r = 0; r < c->nchem; ++r) {
+    const or_reaction_step *st = &c->chem[r];
+    if (st->fuel < 0 || st->fuel >= c->S || st->oxid < 0 || st->oxid >= c->S) return -1;
+    if (!(st->k >= 0) || !isfinite(st->k) || !isfinite(st->Ea_over_R) || !isfinite(st->Q))
+      return -1;
+    for (int s = 1; s < c->S; ++s)
+      if (st->k > 0 && c->sp[s].tau != c->sp[0].tau) return -5;
+  }
   or_model *md = (or_model *)calloc(1, sizeof(or_model));
   if (!md) return -1;
   md->cfg = *c;
   for (int s = 0; s < c->S; ++s) md->sp[s] = c->sp[s];
   md->cfg.sp = md->sp;
+  for (int r = 0; r < c->nchem; ++r) md->chem[r] = c->chem[r];
+  md->cfg.chem = c->nchem > 0 ? md->chem : NULL;
   for (int s = 0; s < c->S; ++s) {
     velocity_set(&md->sp[s], md->vx[s], md->vy[s], md->eta[s]);
     for (int i = 0; i < NV; ++i)
@@ -309,28 +321,51 @@ int or_cell_source(const or_model *md, const double *fc, double *src) {
   double rho, ux, uy, T;
   mixture(md, n, jx, jy, E, &rho, &ux, &uy, &T);
 
-  /* Chemical reaction, Eqs.(1)-(2): one overall step, rate k n^F n^O e^{-Ea/RT}. */
+  /* Chemical reaction, Eqs.(1)-(2): each step r has the rate
+   * omega_r = k_r n^F n^O e^{-Ea_r/RT} and the extent xi_r = omega_r tau
+   * within the relaxation time; the one-step reaction is the mechanism with
+   * one step and the species' own coefficients.  If some reactant would be
+   * consumed beyond its density, every extent is scaled by one common
+   * factor.  Then n* = n + sum_r a_r xi_r and the energy balance
+   * sum (D+I) n* T* = sum (D+I) n T + 2 sum_r Q_r xi_r gives T*. */
   double Ts = T;
   for (int s = 0; s < S; ++s) ns[s] = n[s];
-  if (c->reaction_on) {
-    double nF = n[c->fuel] > 0 ? n[c->fuel] : 0.0;
-    double nO = n[c->oxid] > 0 ? n[c->oxid] : 0.0;
-    double w = c->k_ov * nF * nO * exp(-c->Ea_over_R / T);
-    double xi = w * md->sp[0].tau;
-    for (int s = 0; s < S; ++s) {
-      if (md->sp[s].a < 0) {
-        double avail = n[s] > 0 ? n[s] : 0.0;
-        double cap = avail / (-md->sp[s].a);
-        if (cap < xi) xi = cap;
-      }
+  or_reaction_step one;
+  const or_reaction_step *steps = c->chem;
+  int nr = c->nchem;
+  if (nr == 0 && c->reaction_on) {
+    one.fuel = c->fuel; one.oxid = c->oxid;
+    one.k = c->k_ov; one.Ea_over_R = c->Ea_over_R; one.Q = c->Q;
+    for (int s = 0; s < S; ++s) one.a[s] = md->sp[s].a;
+    steps = &one;
+    nr = 1;
+  }
+  if (nr > 0) {
+    double xi[OR_MAXR];
+    for (int r = 0; r < nr; ++r) {
+      double nF = n[steps[r].fuel] > 0 ? n[steps[r].fuel] : 0.0;
+      double nO = n[steps[r].oxid] > 0 ? n[steps[r].oxid] : 0.0;
+      xi[r] = steps[r].k * nF * nO * exp(-steps[r].Ea_over_R / T) * md->sp[0].tau;
     }
-    double kn = 0, kns = 0;
+    double scale = 1.0;
     for (int s = 0; s < S; ++s) {
-      ns[s] = n[s] + md->sp[s].a * xi;
+      double use = 0.0;
+      for (int r = 0; r < nr; ++r)
+        if (steps[r].a[s] < 0) use += -steps[r].a[s] * xi[r];
+      double avail = n[s] > 0 ? n[s] : 0.0;
+      if (use > avail && avail / use < scale) scale = avail / use;
+    }
+    double heat = 0.0, kn = 0, kns = 0;
+    for (int r = 0; r < nr; ++r) {
+      xi[r] *= scale;
+      heat += 2.0 * steps[r].Q * xi[r];
+      for (int s = 0; s < S; ++s) ns[s] += steps[r].a[s] * xi[r];
+    }
+    for (int s = 0; s < S; ++s) {
       kn += (DIM + md->sp[s].I) * n[s];
       kns += (DIM + md->sp[s].I) * ns[s];
     }
-    Ts = (T * kn + 2.0 * c->Q * xi) / kns;
+    Ts = (T * kn + heat) / kns;
   }
 
   const int force_on = (c->ax != 0.0 || c->ay != 0.0);

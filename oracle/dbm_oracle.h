@@ -36,6 +36,15 @@ typedef struct {
   double eta[4];   /* eta_a, eta_b, eta_c, eta_d                            */
 } or_species;
 
+/* One step of a multi-step mechanism: rate k n^fuel n^oxid exp(-Ea_over_R/T)
+ * (Eq.2 per step), heat Q per unit extent, stoichiometric coefficients a[s]. */
+#define OR_MAXR 4
+typedef struct {
+  int fuel, oxid;
+  double k, Ea_over_R, Q;
+  double a[OR_MAXS];
+} or_reaction_step;
+
 typedef struct {
   int nx, ny;
   double dx, dy, dt;
@@ -49,6 +58,8 @@ typedef struct {
   int scheme;                /* OR_EULER | OR_RK3                               */
   int limiter;               /* OR_LIM_MINMOD (NND) | OR_LIM_NONE               */
   int force_T_mode;          /* OR_FORCE_T_EXACT | OR_FORCE_T_SAME              */
+  int nchem;                 /* > 0: these steps replace the one-step reaction */
+  const or_reaction_step *chem;
 } or_config;
 
 typedef struct or_model or_model;

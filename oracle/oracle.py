@@ -43,6 +43,12 @@ class OrSpecies(ctypes.Structure):
                 ("eta", ctypes.c_double * 4)]
 
 
+class OrReactionStep(ctypes.Structure):
+    _fields_ = [("fuel", ctypes.c_int), ("oxid", ctypes.c_int), ("k", ctypes.c_double),
+                ("Ea_over_R", ctypes.c_double), ("Q", ctypes.c_double),
+                ("a", ctypes.c_double * 16)]
+
+
 class OrConfig(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dy", ctypes.c_double), ("dt", ctypes.c_double), ("bc_x", ctypes.c_int),
@@ -51,7 +57,8 @@ class OrConfig(ctypes.Structure):
                 ("fuel", ctypes.c_int), ("oxid", ctypes.c_int), ("k_ov", ctypes.c_double),
                 ("Ea_over_R", ctypes.c_double), ("Q", ctypes.c_double),
                 ("ax", ctypes.c_double), ("ay", ctypes.c_double), ("scheme", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("force_T_mode", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("force_T_mode", ctypes.c_int),
+                ("nchem", ctypes.c_int), ("chem", ctypes.POINTER(OrReactionStep))]
 
 
 _lib = None
@@ -134,6 +141,17 @@ class Oracle:
         if r is not None:
             c.reaction_on, c.fuel, c.oxid = 1, r["fuel"], r["oxid"]
             c.k_ov, c.Ea_over_R, c.Q = r["k_ov"], r["Ea_over_R"], r.get("Q", 0.0)
+        mech = getattr(prob, "mechanism", None)
+        if mech:
+            steps = (OrReactionStep * len(mech))()
+            for k, st in enumerate(mech):
+                steps[k].fuel, steps[k].oxid = st["fuel"], st["oxid"]
+                steps[k].k, steps[k].Ea_over_R, steps[k].Q = st["k_ov"], st["Ea_over_R"], st.get("Q", 0.0)
+                for j, a in enumerate(st["a"]):
+                    steps[k].a[j] = a
+            c.nchem = len(mech)
+            c.chem = ctypes.cast(steps, ctypes.POINTER(OrReactionStep))
+            self._steps = steps
         c.ax, c.ay = prob.accel
         c.scheme, c.limiter, c.force_T_mode = prob.scheme, prob.limiter, prob.force_T_mode
         self._cfg = c

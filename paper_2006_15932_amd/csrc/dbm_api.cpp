@@ -120,6 +120,25 @@ int validate(const dbm_config *cfgs, int ninst) {
             return fail(DBM_ERR_UNSUPPORTED,
                         who + "a reaction needs one relaxation time for all species");
     }
+    if (c.nchem < 0 || c.nchem > DBM_MAX_REACTION_STEPS || (c.nchem > 0 && !c.chem))
+      return fail(DBM_ERR_ARG, who + "nchem must be 0..4 with a step array");
+    bool any_rate = c.reaction && c.reaction->k_ov > 0;
+    for (int r = 0; r < c.nchem; ++r) {
+      const dbm_reaction_step &st = c.chem[r];
+      if (st.fuel < 0 || st.fuel >= c.nspecies || st.oxidiser < 0 || st.oxidiser >= c.nspecies)
+        return fail(DBM_ERR_ARG, who + "bad reactant indices in a mechanism step");
+      if (!(st.k_ov >= 0) || !std::isfinite(st.k_ov) || !std::isfinite(st.Ea_over_R) ||
+          !std::isfinite(st.Q))
+        return fail(DBM_ERR_ARG, who + "bad constants in a mechanism step");
+      for (int s = 0; s < c.nspecies; ++s)
+        if (!std::isfinite(st.a[s])) return fail(DBM_ERR_ARG, who + "non-finite stoichiometry");
+      any_rate = any_rate || st.k_ov > 0;
+    }
+    if (c.nchem > 0 && any_rate)
+      for (int s = 1; s < c.nspecies; ++s)
+        if (c.species[s].tau != c.species[0].tau)
+          return fail(DBM_ERR_UNSUPPORTED,
+                      who + "a reaction needs one relaxation time for all species");
     if (k > 0) {
       const dbm_config &c0 = cfgs[0];
       if (c.nspecies != c0.nspecies || c.precision != c0.precision ||
@@ -192,6 +211,7 @@ struct dbm_s {
   std::vector<dbm_config> cfg;
   std::vector<std::vector<dbm_species>> species;
   std::vector<dbm_reaction> reaction;
+  std::vector<std::vector<dbm_reaction_step>> chem;
   hipStream_t stream = nullptr, cap = nullptr;
   char *ws = nullptr;
   Layout L;
@@ -484,6 +504,7 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
   h->cfg.assign(cfgs, cfgs + ninst);
   h->species.resize(ninst);
   h->reaction.resize(ninst);
+  h->chem.resize(ninst);
   h->fused_ok = h->S <= kMaxFusedSpecies;
   for (int k = 0; k < ninst; ++k) {
     h->species[k].assign(cfgs[k].species, cfgs[k].species + cfgs[k].nspecies);
@@ -494,6 +515,8 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     } else {
       h->cfg[k].reaction = nullptr;
     }
+    h->chem[k].assign(cfgs[k].chem, cfgs[k].chem + cfgs[k].nchem);
+    h->cfg[k].chem = h->chem[k].empty() ? nullptr : h->chem[k].data();
     if (cfgs[k].bc_x == DBM_BC_WALL) h->fused_ok = false;
     // the one-pass kernel addresses one species' 16 planes with 32-bit offsets
     if ((double)kNV * cfgs[k].nx * (double)cfgs[k].ny * (h->fp32 ? 4.0 : 8.0) >= 4294967296.0)
@@ -508,13 +531,32 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     d.bcx = cfgs[k].bc_x;
     d.bcy = cfgs[k].bc_y;
     d.S = h->S;
-    const dbm_reaction *r = cfgs[k].reaction;
-    d.react = (r && r->k_ov > 0) ? 1 : 0;
-    d.fuel = r ? r->fuel : 0;
-    d.oxid = r ? r->oxidiser : 1;
-    d.k_ov = r ? r->k_ov : 0.0;
-    d.EaR = r ? r->Ea_over_R : 0.0;
-    d.Q2 = r ? 2.0 * r->Q : 0.0;
+    // chemistry: the mechanism's steps, or the one-step reaction as step 0
+    auto add_step = [&](int fuel, int oxid, double kr, double ea, double q, const double *a) {
+      const int r = d.nreact++;
+      d.rfuel[r] = fuel;
+      d.roxid[r] = oxid;
+      d.rk[r] = kr;
+      d.rEa[r] = ea;
+      d.rQ2[r] = 2.0 * q;
+      d.rdK[r] = 0.0;
+      for (int s = 0; s < h->S; ++s) {
+        d.ra[r][s] = a[s];
+        d.rneg[r][s] = a[s] < 0.0 ? -a[s] : 0.0;
+        d.rdK[r] += (2.0 + cfgs[k].species[s].I) * a[s];
+      }
+    };
+    if (cfgs[k].nchem > 0) {
+      for (int r = 0; r < cfgs[k].nchem; ++r) {
+        const dbm_reaction_step &st = cfgs[k].chem[r];
+        if (st.k_ov > 0) add_step(st.fuel, st.oxidiser, st.k_ov, st.Ea_over_R, st.Q, st.a);
+      }
+    } else if (cfgs[k].reaction && cfgs[k].reaction->k_ov > 0) {
+      const dbm_reaction *r = cfgs[k].reaction;
+      double a[kMaxSpecies] = {0};
+      for (int s = 0; s < h->S; ++s) a[s] = cfgs[k].species[s].a_stoich;
+      add_step(r->fuel, r->oxidiser, r->k_ov, r->Ea_over_R, r->Q, a);
+    }
     d.force = (cfgs[k].accel[0] != 0.0 || cfgs[k].accel[1] != 0.0) ? 1 : 0;
     d.fmode = cfgs[k].force_T_mode;
     d.ax = cfgs[k].accel[0];

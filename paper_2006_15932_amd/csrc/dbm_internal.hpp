@@ -9,6 +9,7 @@ namespace dbm {
 
 constexpr int kNV = 16;        // discrete velocities per species (D2V16)
 constexpr int kMaxSpecies = 16;
+constexpr int kMaxReact = 4;          // steps of a multi-step mechanism
 constexpr int kMaxFusedSpecies = 4;   // one-pass kernels are instantiated for S <= 4
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;     // MI355X: 8 accelerator complex dies, one L2 each
@@ -59,8 +60,14 @@ struct InstDev {
   const SpeciesDev *sp;  // S entries
   int nx, ny, bcx, bcy;
   int S;
-  int react, fuel, oxid;
-  double k_ov, EaR, Q2;  // Q2 = 2 Q
+  // Chemistry: nreact steps of Eq.(2) (0 = none); the one-step reaction is
+  // step 0 with the species' stoichiometric coefficients.
+  int nreact;
+  int rfuel[kMaxReact], roxid[kMaxReact];
+  double rk[kMaxReact], rEa[kMaxReact], rQ2[kMaxReact];  // rQ2 = 2 Q_r
+  double rdK[kMaxReact];                   // sum_s (D + I^s) a_r^s
+  double ra[kMaxReact][kMaxSpecies];       // a_r^s
+  double rneg[kMaxReact][kMaxSpecies];     // max(-a_r^s, 0): consumption per extent
   int force, fmode;
   double ax, ay;
   double dt, dx, dy;

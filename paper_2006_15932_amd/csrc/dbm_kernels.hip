@@ -368,11 +368,14 @@ __device__ __forceinline__ void species_moments(SpC &sp, const T *A, const T *X,
 }
 
 // Per-cell scalar chain in FP64: mixture u and T from the species moments
-// (the conservation statement under Eq.6 with Eqs.8-10), then the one-step
-// reaction of Eqs.(1)-(2) within tau (Eq.5): extent xi (n* = n + a xi) and
-// T* from the energy balance with heat Q per unit extent.
+// (the conservation statement under Eq.6 with Eqs.8-10), then the chemistry
+// of Eqs.(1)-(2) within tau (Eq.5): extents xi_r = omega_r tau of the
+// mechanism's steps (one common factor keeps every reactant's consumption
+// within its density), n^s* = n^s + sum_r a_r^s xi_r, and T* from the energy
+// balance with heat Q_r per unit extent.  `dn` is n* - n of the calling
+// wavefront's own species.
 struct CellState {
-  double ux, uy, Tst, xi;
+  double ux, uy, Tst, dn;
 };
 
 // 1/x: hardware estimate refined by Newton steps (each squares the
@@ -396,8 +399,8 @@ template <> __device__ __forceinline__ double arrhenius<float>(double x) {
 
 template <typename T, int S>
 __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*mb)[kWave],
-                                           int lane, CellState &cs) {
-  double rho = 0, px = 0, py = 0, e = 0, kn = 0, nF = 0, nO = 0;
+                                           int lane, int own, CellState &cs) {
+  double rho = 0, px = 0, py = 0, e = 0, kn = 0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const double n = mb[0 * S + s][lane];
@@ -413,23 +416,44 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
   const double ikn = recip<T>(kn);
   const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) * ikn;
   cs.Tst = Tm;
-  cs.xi = 0.0;
-  if (I.react) {
+  cs.dn = 0.0;
+  const int nr = I.nreact;
+  if (nr > 0) {
+    // Everything below is linear in the extents, so the unscaled sums are
+    // accumulated step by step and the common clamp factor (needed only when
+    // some reactant would be overdrawn) multiplies them at the end.
+    const double iT = recip<T>(Tm);
+    double use[S], sdk = 0.0, heat = 0.0, dn = 0.0;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (s == I.fuel) nF = fmax(mb[0 * S + s][lane], 0.0);
-      if (s == I.oxid) nO = fmax(mb[0 * S + s][lane], 0.0);
-    }
-    double xi = I.k_ov * nF * nO * arrhenius<T>(-I.EaR * recip<T>(Tm)) * sp[0].tau;
-    double dkn = 0.0;
+    for (int s = 0; s < S; ++s) use[s] = 0.0;
+#pragma unroll 1
+    for (int r = 0; r < nr; ++r) {
+      const double nF = fmax(mb[I.rfuel[r]][lane], 0.0);
+      const double nO = fmax(mb[I.roxid[r]][lane], 0.0);
+      const double x = I.rk[r] * nF * nO * arrhenius<T>(-I.rEa[r] * iT) * sp[0].tau;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      if (sp[s].a < 0.0) xi = fmin(xi, fmax(mb[0 * S + s][lane], 0.0) * sp[s].inv_neg_a);
-      dkn = fma(sp[s].K, sp[s].a, dkn);
+      for (int s = 0; s < S; ++s) use[s] = fma(I.rneg[r][s], x, use[s]);
+      sdk = fma(I.rdK[r], x, sdk);
+      heat = fma(I.rQ2[r], x, heat);
+      dn = fma(I.ra[r][own], x, dn);
     }
-    // sum (D+I) n* = kn + xi sum (D+I) a
-    cs.Tst = fma(Tm, kn, I.Q2 * xi) * recip<T>(fma(xi, dkn, kn));
-    cs.xi = xi;
+    bool over = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) over = over || use[s] > fmax(mb[0 * S + s][lane], 0.0);
+    if (over) {
+      double scale = 1.0;
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const double avail = fmax(mb[0 * S + s][lane], 0.0);
+        if (use[s] > avail) scale = fmin(scale, avail * recip<T>(use[s]));
+      }
+      sdk *= scale;
+      heat *= scale;
+      dn *= scale;
+    }
+    // sum (D+I) n* T* = sum (D+I) n T + 2 sum_r Q_r xi_r
+    cs.Tst = fma(Tm, kn, heat) * recip<T>(kn + sdk);
+    cs.dn = dn;
   }
 }
 
@@ -690,9 +714,9 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       for (int i = 0; i < kNV; ++i) fnv[i] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, i * plb);
     }
     CellState cs;
-    cell_chain<T, S>(I, sp, mb, lane, cs);
+    cell_chain<T, S>(I, sp, mb, lane, s, cs);
     T df[kNV];
-    collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, fma(me.a, cs.xi, n0), cs.ux,
+    collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + cs.dn, cs.ux,
                        cs.uy, cs.Tst, df);
     const T om = Tab<T>::omega(me);
     T res[kNV];
@@ -840,15 +864,30 @@ __device__ __forceinline__ void plain_feq_cell(const InstDev &I, const T *f, siz
   }
   const double ux = px / rho, uy = py / rho;
   const double Tm = (e - rho * (ux * ux + uy * uy)) / kn;
-  double Tst = Tm, xi = 0.0;
-  if (I.react) {
-    const double nF = fmax(n[I.fuel], 0.0), nO = fmax(n[I.oxid], 0.0);
-    xi = I.k_ov * nF * nO * exp(-I.EaR / Tm) * sp[0].tau;
-    for (int s = 0; s < S; ++s)
-      if (sp[s].a < 0.0) xi = fmin(xi, fmax(n[s], 0.0) / (-sp[s].a));
-    double kns = 0.0;
-    for (int s = 0; s < S; ++s) kns = fma(sp[s].K, fma(sp[s].a, xi, n[s]), kns);
-    Tst = fma(Tm, kn, I.Q2 * xi) / kns;
+  // chemistry (Eqs.(1)-(2), one or several steps): extents, common clamp
+  // factor, n* and T* from the energy balance
+  double Tst = Tm, nst[kMaxSpecies];
+  for (int s = 0; s < S; ++s) nst[s] = n[s];
+  if (I.nreact > 0) {
+    double xi[kMaxReact], scale = 1.0;
+    for (int r = 0; r < I.nreact; ++r) {
+      const double nF = fmax(n[I.rfuel[r]], 0.0), nO = fmax(n[I.roxid[r]], 0.0);
+      xi[r] = I.rk[r] * nF * nO * exp(-I.rEa[r] / Tm) * sp[0].tau;
+    }
+    for (int s = 0; s < S; ++s) {
+      double use = 0.0;
+      for (int r = 0; r < I.nreact; ++r) use = fma(fmax(-I.ra[r][s], 0.0), xi[r], use);
+      const double avail = fmax(n[s], 0.0);
+      if (use > avail) scale = fmin(scale, avail / use);
+    }
+    double heat = 0.0, kns = 0.0;
+    for (int r = 0; r < I.nreact; ++r) {
+      xi[r] *= scale;
+      heat = fma(I.rQ2[r], xi[r], heat);
+      for (int s = 0; s < S; ++s) nst[s] = fma(I.ra[r][s], xi[r], nst[s]);
+    }
+    for (int s = 0; s < S; ++s) kns = fma(sp[s].K, nst[s], kns);
+    Tst = fma(Tm, kn, heat) / kns;
   }
   for (int s = 0; s < S; ++s) {
     // the sixteen closed forms listed after Eq.(14)
@@ -864,7 +903,7 @@ __device__ __forceinline__ void plain_feq_cell(const InstDev &I, const T *f, siz
       h[15] = nn * (th * e2 + v * v * e4);
     };
     double g[kNV], h1[kNV], h2[kNV];
-    fhat(fma(sp[s].a, xi, n[s]), ux, uy, Tst * sp[s].inv_m, g);
+    fhat(nst[s], ux, uy, Tst * sp[s].inv_m, g);
     if (I.force && n[s] > 1e-300) {
       const double us = jx[s] / n[s], vs = jy[s] / n[s];
       const double Ts = sp[s].m * (E[s] / n[s] - us * us - vs * vs) / sp[s].K;

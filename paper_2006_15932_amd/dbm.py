@@ -40,6 +40,12 @@ class dbm_reaction(ctypes.Structure):
                 ("Ea_over_R", ctypes.c_double), ("Q", ctypes.c_double)]
 
 
+class dbm_reaction_step(ctypes.Structure):
+    _fields_ = [("fuel", ctypes.c_int), ("oxidiser", ctypes.c_int), ("k_ov", ctypes.c_double),
+                ("Ea_over_R", ctypes.c_double), ("Q", ctypes.c_double),
+                ("a", ctypes.c_double * 16)]
+
+
 class dbm_config(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("dx", ctypes.c_double),
                 ("dy", ctypes.c_double), ("dt", ctypes.c_double), ("bc_x", ctypes.c_int),
@@ -47,7 +53,8 @@ class dbm_config(ctypes.Structure):
                 ("species", ctypes.POINTER(dbm_species)),
                 ("reaction", ctypes.POINTER(dbm_reaction)), ("accel", ctypes.c_double * 2),
                 ("precision", ctypes.c_int), ("time_scheme", ctypes.c_int),
-                ("limiter", ctypes.c_int), ("force_T_mode", ctypes.c_int)]
+                ("limiter", ctypes.c_int), ("force_T_mode", ctypes.c_int),
+                ("nchem", ctypes.c_int), ("chem", ctypes.POINTER(dbm_reaction_step))]
 
 
 class DbmError(RuntimeError):
@@ -134,6 +141,18 @@ class Configs:
                                  p.reaction["Ea_over_R"], p.reaction.get("Q", 0.0))
                 c.reaction = ctypes.pointer(r)
                 self._keep.append(r)
+            mech = getattr(p, "mechanism", None)
+            if mech:
+                steps = (dbm_reaction_step * len(mech))()
+                for r, st in enumerate(mech):
+                    steps[r].fuel, steps[r].oxidiser = st["fuel"], st["oxid"]
+                    steps[r].k_ov, steps[r].Ea_over_R = st["k_ov"], st["Ea_over_R"]
+                    steps[r].Q = st.get("Q", 0.0)
+                    for j, a in enumerate(st["a"]):
+                        steps[r].a[j] = a
+                c.nchem = len(mech)
+                c.chem = ctypes.cast(steps, ctypes.POINTER(dbm_reaction_step))
+                self._keep.append(steps)
             c.accel[0], c.accel[1] = p.accel
             prec = precision if precision is not None else p.precision
             c.precision = DBM_FP32_BULK if prec in ("fp32", DBM_FP32_BULK) else DBM_FP64

@@ -72,6 +72,7 @@ class Problem:
     bc_x: int = PERIODIC
     bc_y: int = PERIODIC
     reaction: Optional[dict] = None      # fuel, oxid, k_ov, Ea_over_R, Q
+    mechanism: Optional[list] = None     # steps: dict(fuel, oxid, k_ov, Ea_over_R, Q, a)
     accel: tuple = (0.0, 0.0)
     scheme: int = EULER
     limiter: int = LIM_MINMOD
@@ -150,6 +151,32 @@ def reacting(n=256, ny=None, steps=5000, seed=BASE_SEED + 1, tau=2e-5, t_hot=3.0
     xc, yc = np.meshgrid(_centres(nx) - nx / 2.0, _centres(ny) - ny / 2.0)
     T = 1.0 + (t_hot - 1.0) * np.exp(-(xc ** 2 + yc ** 2) / (2.0 * 10.0 ** 2))
     return Problem("reacting", nx, ny, sp, dt=1e-5, reaction=dict(C1_CHEM),
+                   scheme=scheme, steps=steps, precision=precision, n_sp=n_sp,
+                   ux=np.zeros((ny, nx)), uy=np.zeros((ny, nx)), T=T)
+
+
+# --------------------------------------------------------------------------
+# Two-step mechanism with the same overall chemistry as C1:
+#   F + O -> I (intermediate, m = 34),  F + I -> 2 P  (2 F + O -> 2 P overall).
+# --------------------------------------------------------------------------
+TWO_STEP = [dict(fuel=0, oxid=1, k_ov=1e3, Ea_over_R=10.0, Q=5.0, a=(-1.0, -1.0, 1.0, 0.0)),
+            dict(fuel=0, oxid=2, k_ov=5e3, Ea_over_R=8.0, Q=10.0, a=(-1.0, 0.0, -1.0, 2.0))]
+
+
+def two_step(n=64, ny=None, steps=200, seed=BASE_SEED + 5, tau=2e-5, t_hot=3.5,
+             scheme=EULER, precision="fp64", seed_intermediate=1e-3) -> Problem:
+    """Premix of F and O with a little intermediate (mass fraction
+    seed_intermediate), hot Gaussian kernel, periodic, as C1 otherwise."""
+    nx, ny = n, (ny if ny is not None else n)
+    sp = [make_species(2.0, tau=tau), make_species(32.0, tau=tau), make_species(34.0, tau=tau),
+          make_species(18.0, tau=tau)]
+    Y = np.array([1.0 / 9.0, 8.0 / 9.0 - seed_intermediate, seed_intermediate, 0.0])
+    u = Stream(seed).uniform(nx * ny).reshape(ny, nx)
+    rho = 1.0 + 0.01 * (2.0 * u - 1.0)
+    n_sp = np.stack([rho * Y[k] / sp[k].m for k in range(4)])
+    xc, yc = np.meshgrid(_centres(nx) - nx / 2.0, _centres(ny) - ny / 2.0)
+    T = 1.0 + (t_hot - 1.0) * np.exp(-(xc ** 2 + yc ** 2) / (2.0 * 10.0 ** 2))
+    return Problem("two_step", nx, ny, sp, dt=1e-5, mechanism=[dict(st) for st in TWO_STEP],
                    scheme=scheme, steps=steps, precision=precision, n_sp=n_sp,
                    ux=np.zeros((ny, nx)), uy=np.zeros((ny, nx)), T=T)
 

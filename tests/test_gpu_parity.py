@@ -276,3 +276,22 @@ def test_energy_moments_match_oracle(precision, tol):
         scale = np.abs(eg[s]).max()
         assert np.abs((eg[s, 0] - eg[s, 2]) - 0.5 * dg[s, 0]).max() <= 1e-12 * scale
         assert np.abs((eg[s, 4] - eg[s, 6]) - 0.5 * dg[s, 3]).max() <= 1e-12 * scale
+
+
+def test_two_step_mechanism_fp64():
+    """Multi-step chemistry (two steps, four species) on the one-pass kernel
+    and on the plain path."""
+    p = W.two_step(n=70, ny=33)
+    sim = _check_fp64(p, 40)
+    assert sim.get_option(D.DBM_OPT_PATH) == 0
+    _check_fp64(W.two_step(n=29, ny=17), 20, path=1)
+
+
+def test_two_step_mechanism_fp32_within_1e5():
+    p = W.two_step(n=64, steps=400, precision="fp32")
+    sim = gpu_run(p, 400, "fp32")
+    o, fo = oracle_run(p, 400)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    print("fp32 two-step errors", errs, flush=True)
+    for k in ("rho", "u", "T"):
+        assert errs[k] < FP32_TOL, errs

@@ -63,3 +63,20 @@ def test_free_falling_reacting_box_gpu():
     assert abs((t1[-1] - t0[-1]) - release - work) <= 1e-12 * t0[-1]
     o, fo = oracle_run(p, n)
     assert f_error(sim.get_f(), fo) < 1e-10
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-6)])
+def test_two_step_wave_energy_release_gpu(precision, tol):
+    p = V.two_step_wave(precision=precision)
+    sim, t0, rho0 = _sim(p, precision, p.steps)
+    _, t1 = sim.noneq(want_delta=False)
+    rho1 = sim.moments()[0]
+    ms = np.array([s.m for s in p.species])
+    N0 = rho0.sum(axis=(1, 2)) / ms * p.dx * p.dy
+    N1 = rho1.sum(axis=(1, 2)) / ms * p.dx * p.dy
+    release, x1, x2 = V.two_step_release(p, N0, N1)
+    assert x1 > 0 and x2 > 0
+    assert abs((t1[-1] - t0[-1]) - release) <= tol * t0[-1]
+    if precision == "fp64":
+        o, fo = oracle_run(p, p.steps)
+        assert f_error(sim.get_f(), fo) < 1e-10

@@ -605,3 +605,99 @@ def test_heat_flux_matches_chapman_enskog():
     ce = -kappa * (K / 2) * dTdx / m
     err = np.abs(0.5 * delta[0, 3, 0] - ce).max() / np.abs(ce).max()
     assert err < 0.02, err
+
+
+# ---------------------------------------------------------------------------
+# Multi-step chemistry (the text after Eqs.(1)-(2)).
+# ---------------------------------------------------------------------------
+def _mech_rhs(n, U, mech, K, tau):
+    """Moment ODE of a uniform reactor: dn/dt = sum_r a_r omega_r,
+    dU/dt = 2 sum_r Q_r omega_r with U = sum (D+I) n T."""
+    T = U / np.dot(K, n)
+    dn, dU = np.zeros_like(n), 0.0
+    for st in mech:
+        w = st["k_ov"] * max(n[st["fuel"]], 0) * max(n[st["oxid"]], 0) * math.exp(-st["Ea_over_R"] / T)
+        dn += np.array(st["a"][:len(n)]) * w
+        dU += 2.0 * st["Q"] * w
+    return dn, dU
+
+
+def test_two_step_reactor_equals_moment_ode():
+    """A uniform box with the two-step mechanism: the moments follow the
+    mechanism's ODE step for step (Euler), and converge to its continuous
+    solution (scipy, tight tolerance) at first order in dt."""
+    base = W.two_step(n=1, steps=1)
+    sp = base.species
+    K = np.array([2.0 + s.I for s in sp])
+    mech = [dict(st, k_ov=st["k_ov"] * 20) for st in W.TWO_STEP]   # faster, to see progress
+    n0, T0 = np.array([0.05, 0.025, 0.002, 0.0]), 2.0
+    out = {}
+    for dt, steps in [(2e-5, 300), (1e-5, 600)]:
+        p = _uniform(W.Problem("r2", 1, 1, sp, dt=dt, mechanism=mech), n0, 0, 0, T0)
+        o = O.Oracle(p)
+        g = o.run(o.init_equilibrium(*W.fields(p)), steps)
+        rho, _, _, T = o.moments(g)
+        n_or = rho[:, 0, 0] / np.array([s.m for s in sp])
+        n, U = n0.copy(), float(np.dot(K, n0) * T0)
+        for _ in range(steps):
+            dn, dU = _mech_rhs(n, U, mech, K, sp[0].tau)
+            n, U = n + dt * dn, U + dt * dU
+        np.testing.assert_allclose(n_or, n, rtol=1e-11, atol=1e-16)
+        np.testing.assert_allclose(T[0, 0], U / np.dot(K, n), rtol=1e-11)
+        out[dt] = n_or
+
+    def ode(t, y):
+        dn, dU = _mech_rhs(y[:4], y[4], mech, K, sp[0].tau)
+        return np.concatenate([dn, [dU]])
+    sol = solve_ivp(ode, (0, 6e-3), np.concatenate([n0, [np.dot(K, n0) * T0]]),
+                    rtol=1e-12, atol=1e-16, method="DOP853")
+    n_ex = sol.y[:4, -1]
+    assert n_ex[3] > 0.02 * n0[0] and n_ex[2] != n0[2]     # both steps ran
+    e1, e2 = np.abs(out[2e-5] - n_ex).max(), np.abs(out[1e-5] - n_ex).max()
+    assert 1.8 < e1 / e2 < 2.2
+
+
+def test_one_step_mechanism_is_the_single_reaction():
+    """The one-step reaction and the same reaction given as a one-step
+    mechanism (plus a step with zero rate) give identical results."""
+    p = W.reacting(n=12, ny=7, steps=1, precision="fp64", t_hot=3.5)
+    chem = dict(p.reaction, Q=2.0)
+    a = tuple(s.a for s in p.species)
+    single = p.with_(reaction=chem)
+    mech = p.with_(reaction=None, mechanism=[
+        dict(fuel=chem["fuel"], oxid=chem["oxid"], k_ov=chem["k_ov"],
+             Ea_over_R=chem["Ea_over_R"], Q=chem["Q"], a=a),
+        dict(fuel=1, oxid=2, k_ov=0.0, Ea_over_R=1.0, Q=7.0, a=(1.0, -1.0, 0.0))])
+    f = {}
+    for name, q in (("single", single), ("mech", mech)):
+        o = O.Oracle(q)
+        f[name] = o.run(o.init_equilibrium(*W.fields(q)), 30)
+    np.testing.assert_array_equal(f["single"], f["mech"])
+
+
+def test_mechanism_clamp_scales_every_extent():
+    """When the rates would overdraw a reactant within tau, every extent is
+    scaled by one factor: the limiting reactant is used up exactly and the
+    ratio of the steps' extents is that of their rates."""
+    sp = W.two_step(n=1, steps=1).species
+    mech = [dict(st, k_ov=st["k_ov"] * 1e9) for st in W.TWO_STEP]
+    p = _uniform(W.Problem("clamp", 1, 1, sp, mechanism=mech), [0.01, 0.004, 0.003, 0.0], 0, 0, 2.0)
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    src = o.cell_source(f[:, :, 0, 0].reshape(-1))
+    tau = sp[0].tau
+    # n* - n = tau * (sum_i source) per species
+    dn = src.sum(axis=1) * tau
+    n0 = np.array([0.01, 0.004, 0.003, 0.0])
+    T = 2.0
+    w = np.array([st["k_ov"] * n0[st["fuel"]] * n0[st["oxid"]] * math.exp(-st["Ea_over_R"] / T)
+                  for st in mech])
+    xi = w * tau
+    use_F = xi.sum()                                    # both steps consume one F
+    scale = min(1.0, n0[0] / use_F, n0[1] / xi[0], n0[2] / xi[1])
+    xi_c = xi * scale
+    want = np.array([-xi_c[0] - xi_c[1], -xi_c[0], xi_c[0] - xi_c[1], 2 * xi_c[1]])
+    np.testing.assert_allclose(dn, want, rtol=1e-10, atol=1e-18)
+    # here the intermediate limits: step 2 consumes exactly what is there
+    assert abs(xi_c[1] - n0[2]) < 1e-15 and scale < 1e-3
+    assert min(n0 + dn) >= 0.0

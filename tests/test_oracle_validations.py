@@ -76,3 +76,21 @@ def test_free_falling_reacting_box_energy_budget():
     release = p.reaction["Q"] * (nf0 - _fuel_count(o, p, g)) / 2
     assert abs((t1[-1] - t0[-1]) - release - work) <= 1e-12 * t0[-1]
     assert work > 1e-4 * release
+
+
+def test_two_step_wave_energy_release_is_exact():
+    """Two-step mechanism: total energy grows by Q_1 xi_1 + Q_2 xi_2, the
+    extents read off the oxidiser and fuel consumed."""
+    p = V.two_step_wave()
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    _, t0 = o.noneq(f, want_delta=False)
+    ms = np.array([s.m for s in p.species])
+    N0 = o.moments(f)[0].sum(axis=(1, 2)) / ms * p.dx * p.dy
+    g = o.run(f, p.steps)
+    _, t1 = o.noneq(g, want_delta=False)
+    N1 = o.moments(g)[0].sum(axis=(1, 2)) / ms * p.dx * p.dy
+    release, x1, x2 = V.two_step_release(p, N0, N1)
+    assert x1 > 0 and x2 > 0
+    assert abs((t1[-1] - t0[-1]) - release) <= 1e-11 * t0[-1]
+    assert abs(t1[:4].sum() - t0[:4].sum()) <= 1e-12 * t0[:4].sum()

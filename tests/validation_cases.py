@@ -67,3 +67,18 @@ def shock_position(rho, rho1, rho2):
     mid = 0.5 * (rho1 + rho2)
     j = int(np.argmax(rho > mid))
     return j - 1 + (mid - rho[j - 1]) / (rho[j] - rho[j - 1])
+
+
+def two_step_wave(nx=200, steps=600, precision="fp64"):
+    """Periodic 1-D premix with the two-step mechanism (both steps release
+    heat), ignited by a hot Gaussian."""
+    return W.two_step(n=nx, ny=1, steps=steps, precision=precision)
+
+
+def two_step_release(p, n0, n1):
+    """Chemical energy released between species counts n0 and n1 (per
+    species, integrated): step 1 uses one O, so xi_1 = -dN_O; both steps use
+    one F, so xi_2 = -dN_F - xi_1."""
+    x1 = n0[1] - n1[1]
+    x2 = (n0[0] - n1[0]) - x1
+    return p.mechanism[0]["Q"] * x1 + p.mechanism[1]["Q"] * x2, x1, x2
