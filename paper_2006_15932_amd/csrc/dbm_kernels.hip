@@ -372,10 +372,9 @@ __device__ __forceinline__ void species_moments(SpC &sp, const T *A, const T *X,
 // of Eqs.(1)-(2) within tau (Eq.5): extents xi_r = omega_r tau of the
 // mechanism's steps (one common factor keeps every reactant's consumption
 // within its density), n^s* = n^s + sum_r a_r^s xi_r, and T* from the energy
-// balance with heat Q_r per unit extent.  `dn` is n* - n of the calling
-// wavefront's own species.
+// balance with heat Q_r per unit extent.  dn[s] = n^s* - n^s.
 struct CellState {
-  double ux, uy, Tst, dn;
+  double ux, uy, Tst, dn[kMaxFusedSpecies];
 };
 
 // 1/x: hardware estimate refined by Newton steps (each squares the
@@ -399,7 +398,7 @@ template <> __device__ __forceinline__ double arrhenius<float>(double x) {
 
 template <typename T, int S>
 __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*mb)[kWave],
-                                           int lane, int own, CellState &cs) {
+                                           int lane, CellState &cs) {
   double rho = 0, px = 0, py = 0, e = 0, kn = 0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
@@ -416,26 +415,29 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
   const double ikn = recip<T>(kn);
   const double Tm = (e - rho * (cs.ux * cs.ux + cs.uy * cs.uy)) * ikn;
   cs.Tst = Tm;
-  cs.dn = 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) cs.dn[s] = 0.0;
   const int nr = I.nreact;
   if (nr > 0) {
     // Everything below is linear in the extents, so the unscaled sums are
     // accumulated step by step and the common clamp factor (needed only when
     // some reactant would be overdrawn) multiplies them at the end.
     const double iT = recip<T>(Tm);
-    double use[S], sdk = 0.0, heat = 0.0, dn = 0.0;
+    double use[S], sdk = 0.0, heat = 0.0, dn[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) use[s] = 0.0;
+    for (int s = 0; s < S; ++s) use[s] = dn[s] = 0.0;
 #pragma unroll 1
     for (int r = 0; r < nr; ++r) {
       const double nF = fmax(mb[I.rfuel[r]][lane], 0.0);
       const double nO = fmax(mb[I.roxid[r]][lane], 0.0);
       const double x = I.rk[r] * nF * nO * arrhenius<T>(-I.rEa[r] * iT) * sp[0].tau;
 #pragma unroll
-      for (int s = 0; s < S; ++s) use[s] = fma(I.rneg[r][s], x, use[s]);
+      for (int s = 0; s < S; ++s) {
+        use[s] = fma(I.rneg[r][s], x, use[s]);
+        dn[s] = fma(I.ra[r][s], x, dn[s]);
+      }
       sdk = fma(I.rdK[r], x, sdk);
       heat = fma(I.rQ2[r], x, heat);
-      dn = fma(I.ra[r][own], x, dn);
     }
     bool over = false;
 #pragma unroll
@@ -449,11 +451,13 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
       }
       sdk *= scale;
       heat *= scale;
-      dn *= scale;
+#pragma unroll
+      for (int s = 0; s < S; ++s) dn[s] *= scale;
     }
     // sum (D+I) n* T* = sum (D+I) n T + 2 sum_r Q_r xi_r
     cs.Tst = fma(Tm, kn, heat) * recip<T>(kn + sdk);
-    cs.dn = dn;
+#pragma unroll
+    for (int s = 0; s < S; ++s) cs.dn[s] = dn[s];
   }
 }
 
@@ -566,6 +570,18 @@ static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) ==
 constexpr int kXPlanes = 12;
 constexpr int kHaloLanes = 3 * kXPlanes;
 
+// The per-cell chain (mixture u, T, chemistry) is the same for every
+// species of a cell: with DBM_SHARED_CHAIN one wavefront per row (rotating
+// with the row) computes it and publishes it through LDS while the others
+// advance their stencils; a second barrier per row precedes the collision.
+// Off by default: the second barrier and the longer live ranges (247 VGPRs
+// against 217) cost more than the S-fold chain saves (C4 2.34 ms against
+// 2.15 ms per launch).
+#ifndef DBM_SHARED_CHAIN
+#define DBM_SHARED_CHAIN 0
+#endif
+constexpr bool kSharedChain = DBM_SHARED_CHAIN;
+
 // Halo distribution: LDS crossbar gather (1) or lane reads (0), per type.
 #ifndef DBM_GATHER_F32
 #define DBM_GATHER_F32 1
@@ -581,7 +597,8 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 template <typename T, int S, int LIM, bool RKC>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
-                                           T alpha, T beta, double (*mom)[4 * S][kWave]) {
+                                           T alpha, T beta, double (*mom)[4 * S][kWave],
+                                           double (*cst)[3 + S][kWave]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
   // One buffer resource per species and buffer (its 16 planes, under 4 GiB
@@ -713,18 +730,48 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 #pragma unroll
       for (int i = 0; i < kNV; ++i) fnv[i] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, i * plb);
     }
-    CellState cs;
-    cell_chain<T, S>(I, sp, mb, lane, s, cs);
-    T df[kNV];
-    collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + cs.dn, cs.ux,
-                       cs.uy, cs.Tst, df);
+    // Mixture chain: computed here (every wavefront) or by the row's chain
+    // wavefront and published (shared).
+    double ux, uy, Tst, dn_own;
+    double(*cb)[kWave] = cst[k & 1];
+    if (!kSharedChain || s == k % S) {
+      CellState cs;
+      cell_chain<T, S>(I, sp, mb, lane, cs);
+      ux = cs.ux;
+      uy = cs.uy;
+      Tst = cs.Tst;
+      dn_own = cs.dn[0];
+#pragma unroll
+      for (int q = 1; q < S; ++q)
+        if (q == s) dn_own = cs.dn[q];   // wave-uniform select, no indexed array
+      if constexpr (kSharedChain) {
+        cb[0][lane] = cs.ux;
+        cb[1][lane] = cs.uy;
+        cb[2][lane] = cs.Tst;
+#pragma unroll
+        for (int q = 0; q < S; ++q) cb[3 + q][lane] = cs.dn[q];
+      }
+    }
+    // Unshared chain: the collision first, then each plane's stencil is
+    // combined as it is formed.  Shared chain: the stencils first (while the
+    // chain wavefront works), the collision after the second barrier.
     const T om = Tab<T>::omega(me);
-    T res[kNV];
+    T df[kNV], acc[kNV], res[kNV];
+    if constexpr (!kSharedChain)
+      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, ux, uy, Tst, df);
+    auto finish = [&](int i, T a) {
+      res[i] = fma(om, df[i], a);
+      // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
+      // the (small) stage difference
+      if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
+      if constexpr (!kEarlyHalo)
+        if (writer) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+    };
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
       const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
       const T f = c[i];
-      T acc = f;
+      T a = f;
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
@@ -750,7 +797,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
           Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
         }
         const T cx = kEarlyHalo ? cgx[g] : Tab<T>::cgx(me, g);
-        acc = (sx > 0) ? fma(-cx, Dx, acc) : fma(cx, Dx, acc);
+        a = (sx > 0) ? fma(-cx, Dx, a) : fma(cx, Dx, a);
       }
       // y: NND difference from the carried rows; advance the state.
       const T fnew = cur[i];
@@ -758,7 +805,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T dn = fnew - f;
         const T sk = slope_pos<LIM>(y1[i], dn);
         const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
-        acc = fma(-(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g)), Dy, acc);
+        a = fma(-(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g)), Dy, a);
         c[i] = fnew;
         y1[i] = dn;
         y2[i] = sk;
@@ -767,19 +814,27 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T dlo = n1 - f, dhi = fnew - n1;
         const T tk1 = slope_neg<LIM>(dlo, dhi);
         const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
-        acc = fma(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g), Dy, acc);
+        a = fma(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g), Dy, a);
         c[i] = n1;
         y1[i] = fnew;
         y2[i] = tk1;
       } else {
         c[i] = fnew;
       }
-      res[i] = fma(om, df[i], acc);
-      // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
-      // the (small) stage difference
-      if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
-      if constexpr (!kEarlyHalo)
-        if (writer) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+      if constexpr (kSharedChain)
+        acc[i] = a;
+      else
+        finish(i, a);
+    }
+    if constexpr (kSharedChain) {
+      __syncthreads();
+      ux = cb[0][lane];
+      uy = cb[1][lane];
+      Tst = cb[2][lane];
+      dn_own = cb[3 + s][lane];
+      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, ux, uy, Tst, df);
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) finish(i, acc[i]);
     }
     // FP32: one masked block of stores per row (lanes past nx hold wrapped
     // or clamped copies and write nothing), so that the row is one basic
@@ -825,11 +880,12 @@ __global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(co
                                                            int out_idx, T alpha, T beta,
                                                            int remap) {
   __shared__ double mom[2][4 * S][kWave];
+  __shared__ double cst[2][3 + S][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
     fused_tile<T, S, LIM, RKC>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
-                               alpha, beta, mom);
+                               alpha, beta, mom, cst);
     __syncthreads();
   }
 }
