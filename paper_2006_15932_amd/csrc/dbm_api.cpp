@@ -17,10 +17,10 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, const InstDev *insts,
+hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st);
-hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, int *waves_per_cu);
+hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu);
 hipError_t launch_plain(bool fp32, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
                         hipStream_t st);
@@ -192,14 +192,14 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
 }
 
 struct TuneKey {
-  int fp32, S, lim, scheme, bucket, ninst;
+  int fp32, S, lim, scheme, bucket, ninst, split_opt;
   bool operator<(const TuneKey &o) const {
-    return std::tie(fp32, S, lim, scheme, bucket, ninst) <
-           std::tie(o.fp32, o.S, o.lim, o.scheme, o.bucket, o.ninst);
+    return std::tie(fp32, S, lim, scheme, bucket, ninst, split_opt) <
+           std::tie(o.fp32, o.S, o.lim, o.scheme, o.bucket, o.ninst, o.split_opt);
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune_cache;
+std::map<TuneKey, std::pair<int, int>> g_tune_cache;  // -> (rows, form)
 std::mutex g_probe_mu;
 int g_probe_state = 0;  // 0 unknown, 1 ok, -1 failed
 
@@ -221,9 +221,12 @@ struct dbm_s {
       graph_chunk = 16;
   bool fused_ok = false;
   int rows = 0;  // rows per tile in use (0 = not tuned yet)
+  int split_opt = 0;    // DBM_OPT_SPLIT: 0 tuned, 1 full form, 2 split form
+  bool split = false;   // form in use
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
-  int resident = 0;
+  int resident = 0, resident_split = 0;  // workgroups resident on the device, per form
+  int grid_cap() const { return split ? resident_split : resident; }
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   long long since_check = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -269,14 +272,15 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
   if (use_fused(h)) {
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
-      const int grid = std::max(1, std::min(nt, h->resident));
-      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->d_inst(), h->d_tiles(), nt, grid,
+      const int grid = std::max(1, std::min(nt, h->grid_cap()));
+      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->d_inst(), h->d_tiles(), nt, grid,
                           in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
-        const int grid = std::max(1, std::min(nt, h->resident));
-        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->d_inst(), h->d_tiles() + b, nt, grid,
+        const int grid = std::max(1, std::min(nt, h->grid_cap()));
+        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->d_inst(), h->d_tiles() + b,
+                            nt, grid,
                             in_idx, fn_idx, out_idx, alpha, beta, st));
       }
     }
@@ -339,6 +343,10 @@ int time_stage(dbm_handle h, int reps, double *ms) {
 int ensure_tuned(dbm_handle h) {
   if (!use_fused(h)) return DBM_OK;
   int want = h->tile_rows_opt;
+  // form: the split form only when asked for (measured slower than the
+  // full form on every workload here, so the tuner does not try it)
+  int form = h->split_opt == 2 ? 1 : 0;
+  const bool tune_form = false;
   int maxny = 1;
   size_t tot = 0;
   for (int k = 0; k < h->ninst; ++k) {
@@ -346,11 +354,14 @@ int ensure_tuned(dbm_handle h) {
     tot += h->cells(k);
   }
   const TuneKey key{h->fp32 ? 1 : 0, h->S, h->lim, h->scheme,
-                    (int)std::lround(std::log2((double)tot + 1.0)), h->ninst};
+                    (int)std::lround(std::log2((double)tot + 1.0)), h->ninst, h->split_opt};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
-    if (it != g_tune_cache.end()) want = it->second;
+    if (it != g_tune_cache.end()) {
+      want = it->second.first;
+      form = it->second.second;
+    }
   }
   if (want <= 0) {
     if (h->scheme == DBM_TVD_RK3) {  // give the timed stage realistic inputs
@@ -361,25 +372,32 @@ int ensure_tuned(dbm_handle h) {
     }
     const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
     double best = 1e300;
-    int best_rows = 1;
-    for (int r : cands) {
-      if (r > 2 * maxny && r > 1) break;
-      build_tiles(h, r);
-      int rc = upload_tiles(h);
-      if (rc) return rc;
-      double ms = 0.0;
-      if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
-      if ((rc = time_stage(h, 3, &ms))) return rc;
-      if (ms < best) {
-        best = ms;
-        best_rows = r;
+    int best_rows = 1, best_form = form;
+    for (int f = 0; f < 2; ++f) {
+      if (!tune_form && f != form) continue;
+      h->split = f == 1;
+      for (int r : cands) {
+        if (r > 2 * maxny && r > 1) break;
+        build_tiles(h, r);
+        int rc = upload_tiles(h);
+        if (rc) return rc;
+        double ms = 0.0;
+        if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
+        if ((rc = time_stage(h, 3, &ms))) return rc;
+        if (ms < best) {
+          best = ms;
+          best_rows = r;
+          best_form = f;
+        }
       }
     }
     want = best_rows;
+    form = best_form;
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = want;
+    g_tune_cache[key] = std::make_pair(want, form);
   }
-  if (want != h->rows || h->tiles.empty()) {
+  if (want != h->rows || h->tiles.empty() || h->split != (form == 1)) {
+    h->split = form == 1;
     build_tiles(h, want);
     int rc = upload_tiles(h);
     if (rc) return rc;
@@ -587,15 +605,17 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
   if ((rc = run_probe(h))) return bail(rc);
   if (g_probe_state < 0) h->fused_ok = false;
   if (h->fused_ok) {
-    int per_cu = 0, dev = 0;
+    int per_cu = 0, per_cu_split = 0, dev = 0;
     hipDeviceProp_t prop;
-    if ((e = fused_occupancy(h->fp32, h->S, h->lim, h->scheme == DBM_TVD_RK3, &per_cu)) !=
-            hipSuccess ||
+    const bool rk3 = h->scheme == DBM_TVD_RK3;
+    if ((e = fused_occupancy(h->fp32, h->S, h->lim, rk3, false, &per_cu)) != hipSuccess ||
+        (e = fused_occupancy(h->fp32, h->S, h->lim, rk3, true, &per_cu_split)) != hipSuccess ||
         (e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
       return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
-    h->resident = std::max(kNumXcd, per_cu * prop.multiProcessorCount);
-    h->resident = (h->resident / kNumXcd) * kNumXcd;
+    auto round_xcd = [](int r) { return std::max(kNumXcd, (r / kNumXcd) * kNumXcd); };
+    h->resident = round_xcd(per_cu * prop.multiProcessorCount);
+    h->resident_split = round_xcd(per_cu_split * prop.multiProcessorCount);
   }
   *out = h;
   return DBM_OK;
@@ -788,6 +808,12 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       if (value < 1 || value > 4096) return fail(DBM_ERR_ARG, "graph chunk out of range");
       h->graph_chunk = value;
       break;
+    case DBM_OPT_SPLIT:
+      if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "split must be 0, 1 or 2");
+      h->split_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
     default: return fail(DBM_ERR_ARG, "unknown or read-only option");
   }
   clear_graphs(h);
@@ -803,7 +829,8 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_CHECK_EVERY: *value = h->check_every; break;
     case DBM_OPT_BATCH_MODE: *value = h->batch_mode; break;
     case DBM_OPT_GRAPH_CHUNK: *value = h->graph_chunk; break;
-    case DBM_OPT_PERSISTENT: *value = h->resident; break;
+    case DBM_OPT_PERSISTENT: *value = h->grid_cap(); break;
+    case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;

@@ -396,17 +396,18 @@ template <> __device__ __forceinline__ double arrhenius<float>(double x) {
   return (double)__expf((float)x);
 }
 
-template <typename T, int S>
-__device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*mb)[kWave],
-                                           int lane, CellState &cs) {
+// `mom(q, s)` returns moment q (n, j_x, j_y, E) of species s at this lane's
+// cell.
+template <typename T, int S, typename Mom>
+__device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, Mom mom, CellState &cs) {
   double rho = 0, px = 0, py = 0, e = 0, kn = 0;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    const double n = mb[0 * S + s][lane];
+    const double n = mom(0, s);
     rho = fma(sp[s].m, n, rho);
-    px = fma(sp[s].m, mb[1 * S + s][lane], px);
-    py = fma(sp[s].m, mb[2 * S + s][lane], py);
-    e = fma(sp[s].m, mb[3 * S + s][lane], e);
+    px = fma(sp[s].m, mom(1, s), px);
+    py = fma(sp[s].m, mom(2, s), py);
+    e = fma(sp[s].m, mom(3, s), e);
     kn = fma(sp[s].K, n, kn);
   }
   const double irho = recip<T>(rho);
@@ -428,8 +429,8 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
     for (int s = 0; s < S; ++s) use[s] = dn[s] = 0.0;
 #pragma unroll 1
     for (int r = 0; r < nr; ++r) {
-      const double nF = fmax(mb[I.rfuel[r]][lane], 0.0);
-      const double nO = fmax(mb[I.roxid[r]][lane], 0.0);
+      const double nF = fmax(mom(0, I.rfuel[r]), 0.0);
+      const double nO = fmax(mom(0, I.roxid[r]), 0.0);
       const double x = I.rk[r] * nF * nO * arrhenius<T>(-I.rEa[r] * iT) * sp[0].tau;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
@@ -441,12 +442,12 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
     }
     bool over = false;
 #pragma unroll
-    for (int s = 0; s < S; ++s) over = over || use[s] > fmax(mb[0 * S + s][lane], 0.0);
+    for (int s = 0; s < S; ++s) over = over || use[s] > fmax(mom(0, s), 0.0);
     if (over) {
       double scale = 1.0;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const double avail = fmax(mb[0 * S + s][lane], 0.0);
+        const double avail = fmax(mom(0, s), 0.0);
         if (use[s] > avail) scale = fmin(scale, avail * recip<T>(use[s]));
       }
       sdk *= scale;
@@ -461,6 +462,38 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
   }
 }
 
+// block_feq restricted to the axis group g0 (0 or 2) and the diagonal group
+// g0 + 1: the eight values of planes 4 g0 .. 4 g0 + 7.
+template <typename T>
+__device__ __forceinline__ void block_feq_pair(SpC &sp, const T *r, int g0, T *f) {
+  const T DBM_CONST *KA = launder_after(Tab<T>::KA(sp), r[0]);
+  const T DBM_CONST *KE = launder_after(Tab<T>::KE(sp), r[8]);
+  const T DBM_CONST *KB1 = launder_after(Tab<T>::KB1(sp), r[4]);
+  const T DBM_CONST *KB2 = launder_after(Tab<T>::KB2(sp), r[6]);
+#pragma unroll
+  for (int lg = 0; lg < 2; ++lg) {
+    const int g = g0 + lg;
+    T al = KA[g * 4] * r[0], xi = KE[g * 4] * r[8], ps = KE[g * 4] * r[12];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      al = fma(KA[g * 4 + j], r[j], al);
+      xi = fma(KE[g * 4 + j], r[8 + j], xi);
+      ps = fma(KE[g * 4 + j], r[12 + j], ps);
+    }
+    T *o = f + 4 * lg;
+    if (lg == 0) {  // axis group: B from the (v_x^2 - v_y^2) rows
+      const T be = fma(KB1[g0 + 1], r[5], KB1[g0] * r[4]);
+      const T p = al + be, m = al - be;
+      o[0] = p + xi; o[1] = m + ps; o[2] = p - xi; o[3] = m - ps;
+    } else {        // diagonal group: B from the v_x v_y rows
+      const T be = fma(KB2[g0 + 1], r[7], KB2[g0] * r[6]);
+      const T p = al + be, m = al - be;
+      const T sm = xi + ps, df = xi - ps;
+      o[0] = p + sm; o[1] = m - df; o[2] = p - sm; o[3] = m + df;
+    }
+  }
+}
+
 // Collision + reaction + force of one species in moment space:
 //   df = f^eq(n*, u, T*) + [f^eq(n, u+, T+) - f^eq(n, u^s, T^s)] - f
 //      = M^{-1} (g - M f)
@@ -469,10 +502,10 @@ __device__ __forceinline__ void cell_chain(const InstDev &I, SpC *sp, double (*m
 // so the update conserves them to the rounding of the (small) difference
 // itself; the other rows are differenced in the storage precision.
 template <typename T>
-__device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const T *A,
-                                                const T *B, const T *X, const T *Y, double n,
-                                                double jx, double jy, double E, double ns,
-                                                double ux, double uy, double Tst, T *df) {
+__device__ __forceinline__ void collision_rhs(const InstDev &I, SpC &sp, const T *A,
+                                              const T *B, const T *X, const T *Y, double n,
+                                              double jx, double jy, double E, double ns,
+                                              double ux, double uy, double Tst, T *d) {
   const double K = sp.K, th = Tst * sp.inv_m, u2 = ux * ux + uy * uy;
   T r[16];
   eq_rhs<T>((T)ns, (T)ux, (T)uy, (T)th, (T)K, r);
@@ -500,7 +533,6 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const
   const T DBM_CONST *MB1 = launder_after(Tab<T>::MB1(sp), r[4]);
   const T DBM_CONST *MB2 = launder_after(Tab<T>::MB2(sp), r[6]);
   const T DBM_CONST *ME = launder_after(Tab<T>::ME(sp), r[9]);
-  T d[16];
   d[0] = (T)d0;
   d[1] = (T)d1;
   d[8] = (T)d8;
@@ -532,6 +564,15 @@ __device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const
     for (int k = 0; k < 16; ++k)
       if (k != 0 && k != 1 && k != 8 && k != 12) d[k] += (T)fd[k];
   }
+}
+
+template <typename T>
+__device__ __forceinline__ void collision_delta(const InstDev &I, SpC &sp, const T *A,
+                                                const T *B, const T *X, const T *Y, double n,
+                                                double jx, double jy, double E, double ns,
+                                                double ux, double uy, double Tst, T *df) {
+  T d[16];
+  collision_rhs<T>(I, sp, A, B, X, Y, n, jx, jy, E, ns, ux, uy, Tst, d);
   block_feq<T>(sp, d, df);
 }
 
@@ -736,7 +777,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     double(*cb)[kWave] = cst[k & 1];
     if (!kSharedChain || s == k % S) {
       CellState cs;
-      cell_chain<T, S>(I, sp, mb, lane, cs);
+      cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
       ux = cs.ux;
       uy = cs.uy;
       Tst = cs.Tst;
@@ -860,6 +901,247 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   }
 }
 
+// Split form of the one-pass stage, for grids too small to fill the chip:
+// each species is carried by two wavefronts, half h holding the planes of
+// groups 2h and 2h+1 (planes 8h .. 8h+7: one axis group and one diagonal
+// group, so both halves have the same plane types and run the same code).
+// Per row each half publishes its orbit parts and partial FP64 moments
+// through LDS; after the row's barrier both halves form the species' full
+// moments, the mixture chain and the moment-space collision, and each
+// updates its own eight planes.  Twice the wavefronts at about two thirds of
+// the work each.
+constexpr int kHalfPlanes = 8;
+constexpr int kHalfXPlanes = 6;                     // local planes 0, 2, 4..7
+constexpr int kHalfHaloLanes = 3 * kHalfXPlanes;
+
+template <typename T, int S, int LIM, bool RKC>
+__device__ __forceinline__ void fused_tile_split(const InstDev &I, const int s, const int h,
+                                                 int x0, int y0, int rows, int in_idx,
+                                                 int fn_idx, int out_idx, T alpha,
+                                                 T (*orb)[S][16][kWave],
+                                                 double (*pm)[4][S][2][kWave]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nx = I.nx, ny = I.ny, bcy = I.bcy;
+  constexpr uint32_t es = sizeof(T);
+  const size_t plane = (size_t)nx * (size_t)ny;
+  const uint32_t plb = (uint32_t)plane * es;       // bytes per plane
+  const uint32_t spb = kNV * plb;                  // bytes per species
+  const rsrc_t rin = make_rsrc((const T *)I.buf[in_idx] + (size_t)s * kNV * plane, spb);
+  const rsrc_t rfn = make_rsrc((const T *)I.buf[fn_idx] + (size_t)s * kNV * plane, spb);
+  const rsrc_t rout = make_rsrc((const T *)I.buf[out_idx] + (size_t)s * kNV * plane, spb);
+  const uint32_t pob = (uint32_t)(kHalfPlanes * h) * plb;   // this half's first plane
+  const int col = x0 + lane;
+  const int lcol = map_x(col, nx, I.bcx);
+  const bool writer = col < nx;
+  const int yend = y0 + rows;
+
+  // Local plane j is plane 8h + j; its y-mirror stays in its group.
+  auto load = [&](int j, int roff, bool flip) -> T {
+    const uint32_t p = flip ? mirror_y(j) : j;
+    return bload<T>(rin, (uint32_t)(roff + lcol) * es, pob + p * plb);
+  };
+  // Compact halo of the six x-moving planes, as in the full form.
+  uint32_t hoff;
+  {
+    const int hl = lane < kHalfHaloLanes ? lane : 0;
+    const int j = hl / 3, w = hl - 3 * j;
+    const int hp = xplane(j);
+    const int hcol = w == 0 ? x0 - 1 : (w == 2 ? x0 + kWave : (plane_sx(hp) > 0 ? x0 - 2 : x0 + kWave + 1));
+    hoff = pob + (uint32_t)hp * plb + (uint32_t)map_x(hcol, nx, I.bcx) * es;
+  }
+  const int hidx1 = lane == kWave - 1 ? 8 : 0;
+
+  T c[kHalfPlanes], y1[kHalfPlanes], y2[kHalfPlanes];
+  {
+    bool fm2, fm1, f0, fp1;
+    const int rm2 = map_y(y0 - 2, ny, bcy, fm2) * nx, rm1 = map_y(y0 - 1, ny, bcy, fm1) * nx;
+    const int r0 = map_y(y0, ny, bcy, f0) * nx, rp1 = map_y(y0 + 1, ny, bcy, fp1) * nx;
+#pragma unroll
+    for (int j = 0; j < kHalfPlanes; ++j) {
+      const int sy = plane_sy(j);
+      if (sy > 0) {
+        const T a = load(j, rm2, fm2), b = load(j, rm1, fm1), cc = load(j, r0, f0);
+        c[j] = cc;
+        y1[j] = cc - b;
+        y2[j] = slope_pos<LIM>(b - a, cc - b);
+      } else if (sy < 0) {
+        const T a = load(j, rm1, fm1), cc = load(j, r0, f0), n1 = load(j, rp1, fp1);
+        c[j] = cc;
+        y1[j] = n1;
+        y2[j] = slope_neg<LIM>(cc - a, n1 - cc);
+      } else {
+        c[j] = load(j, r0, f0);
+        y1[j] = T(0);
+        y2[j] = T(0);
+      }
+    }
+  }
+  auto issue = [&](int k, T *dst, T &halo) {
+    bool fa, fb;
+    const int ra = map_y(k + 1, ny, bcy, fa) * nx, rb = map_y(k + 2, ny, bcy, fb) * nx;
+#pragma unroll
+    for (int j = 0; j < kHalfPlanes; ++j)
+      dst[j] = plane_sy(j) < 0 ? load(j, rb, fb) : load(j, ra, fa);
+    halo = bload<T>(rin, hoff + (uint32_t)(k * nx) * es, 0);
+  };
+
+  T ring[kPrefetch][kHalfPlanes];
+  T hring[kPrefetch];
+  auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
+    if (k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
+    const int rk = k * nx;
+    SpC *sp = launder(as_const(I.sp));
+    SpC &me = sp[s];
+    T h1[kHalfXPlanes], h2[kHalfXPlanes];
+#pragma unroll
+    for (int j = 0; j < kHalfXPlanes; ++j) {
+      if constexpr (kHaloGather<T>) {
+        h1[j] = bperm(hidx1 + 12 * j, hcur);
+        h2[j] = bperm(4 + 12 * j, hcur);
+      } else {
+        h1[j] = lane == 0 ? readlane(hcur, 3 * j) : readlane(hcur, 3 * j + 2);
+        h2[j] = readlane(hcur, 3 * j + 1);
+      }
+    }
+    T cgx[2], cgy[2];
+#pragma unroll
+    for (int lg = 0; lg < 2; ++lg) {
+      cgx[lg] = Tab<T>::cgx(me, 2 * h + lg);
+      cgy[lg] = Tab<T>::cgy(me, 2 * h + lg);
+    }
+    // Own orbit parts and partial moments to LDS; one barrier.
+    T (*ob)[kWave] = orb[k & 1][s];
+    double(*pb)[S][2][kWave] = pm[k & 1];
+    {
+      T lA[2], lB[2], lX[2], lY[2];
+#pragma unroll
+      for (int lg = 0; lg < 2; ++lg) {
+        const T c0 = c[4 * lg], c1 = c[4 * lg + 1], c2 = c[4 * lg + 2], c3 = c[4 * lg + 3];
+        const T s02 = c0 + c2, s13 = c1 + c3;
+        lA[lg] = s02 + s13;
+        lB[lg] = s02 - s13;
+        if (lg == 0) {
+          lX[lg] = c0 - c2; lY[lg] = c1 - c3;
+        } else {
+          lX[lg] = (c0 + c3) - (c1 + c2); lY[lg] = (c0 + c1) - (c2 + c3);
+        }
+      }
+      double pn = 0.0, pjx = 0.0, pjy = 0.0, pE = 0.0;
+#pragma unroll
+      for (int lg = 0; lg < 2; ++lg) {
+        const int g = 2 * h + lg;
+        const double a = (double)lA[lg];
+        pn += a;
+        pjx = fma(me.vg[g], (double)lX[lg], pjx);
+        pjy = fma(me.vg[g], (double)lY[lg], pjy);
+        pE = fma(me.qg[g], a, pE);
+        ob[0 * 4 + g][lane] = lA[lg];
+        ob[1 * 4 + g][lane] = lB[lg];
+        ob[2 * 4 + g][lane] = lX[lg];
+        ob[3 * 4 + g][lane] = lY[lg];
+      }
+      pb[0][s][h][lane] = pn;
+      pb[1][s][h][lane] = pjx;
+      pb[2][s][h][lane] = pjy;
+      pb[3][s][h][lane] = pE;
+    }
+    __syncthreads();
+    T oA[4], oB[4], oX[4], oY[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      oA[g] = ob[0 * 4 + g][lane];
+      oB[g] = ob[1 * 4 + g][lane];
+      oX[g] = ob[2 * 4 + g][lane];
+      oY[g] = ob[3 * 4 + g][lane];
+    }
+    auto mom = [&](int q, int sp_) { return pb[q][sp_][0][lane] + pb[q][sp_][1][lane]; };
+    const double n0 = mom(0, s), jx0 = mom(1, s), jy0 = mom(2, s), E0 = mom(3, s);
+    T fnv[kHalfPlanes];
+    if constexpr (RKC) {
+#pragma unroll
+      for (int j = 0; j < kHalfPlanes; ++j)
+        fnv[j] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, pob + j * plb);
+    }
+    CellState cs;
+    cell_chain<T, S>(I, sp, mom, cs);
+    double dn_own = cs.dn[0];
+#pragma unroll
+    for (int q = 1; q < S; ++q)
+      if (q == s) dn_own = cs.dn[q];
+    T d[16], df[kHalfPlanes];
+    collision_rhs<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, cs.ux, cs.uy,
+                     cs.Tst, d);
+    block_feq_pair<T>(me, d, 2 * h, df);
+    const T om = Tab<T>::omega(me);
+    T res[kHalfPlanes];
+#pragma unroll
+    for (int j = 0; j < kHalfPlanes; ++j) {
+      const int lg = j >> 2, sx = plane_sx(j), sy = plane_sy(j);
+      const T f = c[j];
+      T a = f;
+      if (sx != 0) {
+        const int jx = xplane_index(j);
+        const T dl = f - h1[jx];
+        const T e = sx > 0 ? h1[jx] - h2[jx] : h2[jx] - h1[jx];
+        const T dp = shl1e(f, h1[jx]) - f;
+        T Dx;
+        if (sx > 0) {
+          const T sle = slope_pos<LIM>(e, dl);
+          const T d0 = shr1e(dp, dl);
+          const T sl = slope_pos<LIM>(d0, dp);
+          Dx = fma(T(0.5), sl - shr1e(sl, sle), d0);
+        } else {
+          const T sle = slope_neg<LIM>(dl, dp);
+          const T dhi = shl1e(dp, e);
+          const T sl = slope_neg<LIM>(dp, dhi);
+          Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
+        }
+        a = (sx > 0) ? fma(-cgx[lg], Dx, a) : fma(cgx[lg], Dx, a);
+      }
+      const T fnew = cur[j];
+      if (sy > 0) {
+        const T dn = fnew - f;
+        const T sk = slope_pos<LIM>(y1[j], dn);
+        const T Dy = y1[j] + T(0.5) * (sk - y2[j]);
+        a = fma(-cgy[lg], Dy, a);
+        c[j] = fnew;
+        y1[j] = dn;
+        y2[j] = sk;
+      } else if (sy < 0) {
+        const T n1 = y1[j];
+        const T dlo = n1 - f, dhi = fnew - n1;
+        const T tk1 = slope_neg<LIM>(dlo, dhi);
+        const T Dy = dlo - T(0.5) * (tk1 - y2[j]);
+        a = fma(cgy[lg], Dy, a);
+        c[j] = n1;
+        y1[j] = fnew;
+        y2[j] = tk1;
+      } else {
+        c[j] = fnew;
+      }
+      res[j] = fma(om, df[j], a);
+      if constexpr (RKC) res[j] = fma(alpha, fnv[j] - res[j], res[j]);
+    }
+    if (writer) {
+#pragma unroll
+      for (int j = 0; j < kHalfPlanes; ++j)
+        bstore(rout, res[j], (uint32_t)(rk + col) * es, pob + j * plb);
+    }
+  };
+
+#pragma unroll
+  for (int d = 0; d < kPrefetch - 1; ++d)
+    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d]);
+  for (int k = y0; k < yend; k += kPrefetch) {
+#pragma unroll
+    for (int d = 0; d < kPrefetch; ++d) {
+      if (k + d < yend)
+        row(k + d, ring[d], hring[d], ring[(d + kPrefetch - 1) % kPrefetch],
+            hring[(d + kPrefetch - 1) % kPrefetch]);
+    }
+  }
+}
+
 // Minimum resident wavefronts per SIMD requested from the register allocator.
 #ifndef DBM_MIN_WAVES_F32
 #define DBM_MIN_WAVES_F32 2
@@ -889,6 +1171,36 @@ __global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(co
     __syncthreads();
   }
 }
+
+#ifndef DBM_MIN_WAVES_SPLIT_F32
+#define DBM_MIN_WAVES_SPLIT_F32 3
+#endif
+#ifndef DBM_MIN_WAVES_SPLIT_F64
+#define DBM_MIN_WAVES_SPLIT_F64 1
+#endif
+template <typename T> struct OccSplit;
+template <> struct OccSplit<float> { static constexpr int kMinWaves = DBM_MIN_WAVES_SPLIT_F32; };
+template <> struct OccSplit<double> { static constexpr int kMinWaves = DBM_MIN_WAVES_SPLIT_F64; };
+
+// Split form: one workgroup = 2S wavefronts, wavefront 2s+h advancing half h
+// of species s of a tile.
+template <typename T, int S, int LIM, bool RKC>
+__global__ __launch_bounds__(kWave * 2 * S, OccSplit<T>::kMinWaves) void k_fused_split(
+    const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
+    int fn_idx, int out_idx, T alpha, T beta, int remap) {
+  __shared__ T orb[2][S][16][kWave];
+  __shared__ double pm[2][4][S][2][kWave];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const int s = w >> 1, h = w & 1;
+  (void)beta;
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
+    fused_tile_split<T, S, LIM, RKC>(insts[t.inst], s, h, t.x0, t.y0, t.rows, in_idx, fn_idx,
+                                     out_idx, alpha, orb, pm);
+    __syncthreads();
+  }
+}
+
 
 // ---------------------------------------------------------------------------
 // Plain path: one thread per cell for the equilibrium (dense FP64 M^{-1}),
@@ -1420,12 +1732,20 @@ static int xcd_remap_flag() {
   return g_xcd_remap;
 }
 
+static bool g_split = false;  // set by launch_fused for the templates below
+
 template <typename T, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                                  int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                                  hipStream_t st) {
-  hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave * S), 0, st, insts,
-                     tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta, g_xcd_remap);
+  if (g_split)
+    hipLaunchKernelGGL((k_fused_split<T, S, LIM, RKC>), dim3(grid), dim3(kWave * 2 * S), 0, st,
+                       insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+                       g_xcd_remap);
+  else
+    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave * S), 0, st,
+                       insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+                       g_xcd_remap);
   return hipGetLastError();
 }
 
@@ -1461,24 +1781,27 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
   }
 }
 
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, const InstDev *insts,
+hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st) {
   xcd_remap_flag();
+  g_split = split;
   return fp32 ? launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
                                       out_idx, alpha, beta, st)
               : launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
                                        out_idx, alpha, beta, st);
 }
 
-hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, int *waves_per_cu) {
+hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
   const void *fn = nullptr;
-#define DBM_PICK(T, SS)                                                                         \
+#define DBM_PICK1(K, T, SS)                                                                     \
   fn = lim == DBM_LIM_MINMOD                                                                   \
-           ? (rkc ? (const void *)k_fused_stage<T, SS, DBM_LIM_MINMOD, true>                   \
-                  : (const void *)k_fused_stage<T, SS, DBM_LIM_MINMOD, false>)                 \
-           : (rkc ? (const void *)k_fused_stage<T, SS, DBM_LIM_NONE, true>                     \
-                  : (const void *)k_fused_stage<T, SS, DBM_LIM_NONE, false>)
+           ? (rkc ? (const void *)K<T, SS, DBM_LIM_MINMOD, true>                               \
+                  : (const void *)K<T, SS, DBM_LIM_MINMOD, false>)                             \
+           : (rkc ? (const void *)K<T, SS, DBM_LIM_NONE, true>                                 \
+                  : (const void *)K<T, SS, DBM_LIM_NONE, false>)
+#define DBM_PICK(T, SS)                                                                         \
+  if (split) { DBM_PICK1(k_fused_split, T, SS); } else { DBM_PICK1(k_fused_stage, T, SS); }
   if (fp32) {
     switch (S) { case 1: DBM_PICK(float, 1); break; case 2: DBM_PICK(float, 2); break;
                  case 3: DBM_PICK(float, 3); break; case 4: DBM_PICK(float, 4); break;
@@ -1489,7 +1812,9 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, int *waves_per_c
                  default: return hipErrorInvalidValue; }
   }
 #undef DBM_PICK
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S, 0);
+#undef DBM_PICK1
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S * (split ? 2 : 1),
+                                                      0);
 }
 
 static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }

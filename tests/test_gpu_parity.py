@@ -295,3 +295,46 @@ def test_two_step_mechanism_fp32_within_1e5():
     print("fp32 two-step errors", errs, flush=True)
     for k in ("rho", "u", "T"):
         assert errs[k] < FP32_TOL, errs
+
+
+SPLIT = {D.DBM_OPT_SPLIT: 2}
+
+
+@pytest.mark.parametrize("case", ["reacting_rk3", "rt_walls_force", "shear4", "two_step",
+                                  "ragged", "outflow"])
+def test_split_form_fp64(case):
+    """The two-wavefronts-per-species form of the one-pass kernel against the
+    oracle, on every boundary type, both schemes, force, chemistry and
+    ragged sizes."""
+    p, steps = {
+        "reacting_rk3": (small_reacting(nx=130, ny=37).with_(scheme=W.RK3), 30),
+        "rt_walls_force": (small_rt(), 40),
+        "shear4": (small_shear(nx=90, ny=40), 30),
+        "two_step": (W.two_step(n=70, ny=33), 30),
+        "ragged": (small_reacting(nx=65, ny=3), 12),
+        "outflow": (small_reacting(nx=61, ny=33).with_(bc_x=W.OUTFLOW, bc_y=W.OUTFLOW), 20),
+    }[case]
+    sim = _check_fp64(p, steps, options=SPLIT)
+    assert sim.get_option(D.DBM_OPT_SPLIT) == 2 and sim.get_option(D.DBM_OPT_PATH) == 0
+
+
+def test_split_form_fp32_within_1e5():
+    p = W.reacting(n=64, steps=500, precision="fp32")
+    sim = gpu_run(p, 500, "fp32", options=SPLIT)
+    assert sim.get_option(D.DBM_OPT_SPLIT) == 2
+    o, fo = oracle_run(p, 500)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    for k in ("rho", "u", "T"):
+        assert errs[k] < FP32_TOL, errs
+
+
+def test_split_form_tile_shape_does_not_change_bits():
+    p = small_reacting(nx=125, ny=41)
+    ref = None
+    for rows in (1, 4, 32):
+        sim = gpu_run(p, 15, "fp64", tile_rows=rows, options=SPLIT)
+        f = sim.get_f()
+        if ref is None:
+            ref = f
+        else:
+            np.testing.assert_array_equal(f, ref)
