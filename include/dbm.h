@@ -180,10 +180,14 @@ enum {
                                1 one launch per instance (comparison mode)     */
   DBM_OPT_GRAPH_CHUNK = 6,  /* steps captured per graph (default 16)          */
   DBM_OPT_PERSISTENT = 7,   /* read only: resident workgroups of a launch      */
-  DBM_OPT_SPLIT = 8         /* form of the one-pass kernel: 0 default (= 1),
+  DBM_OPT_SPLIT = 8,        /* form of the one-pass kernel: 0 default (= 1),
                                1 one wavefront per species, 2 two wavefronts
                                per species, each holding 8 of the 16 planes;
                                get: 1 or 2 in use */
+  DBM_OPT_PIPELINE = 9      /* FP32 full form: row k+1's collision formed
+                               while row k's stencils are; 0 tuned with the
+                               tile rows (default; off when the rows are set),
+                               1 off, 2 on; get: 1 or 2 in use */
 };
 int dbm_set_option(dbm_handle h, int option, int value);
 int dbm_get_option(dbm_handle h, int option, int *value);

@@ -17,7 +17,8 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, const InstDev *insts,
+hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, bool pipe,
+                        const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st);
 hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu);
@@ -223,6 +224,8 @@ struct dbm_s {
   int rows = 0;  // rows per tile in use (0 = not tuned yet)
   int split_opt = 0;    // DBM_OPT_SPLIT: 0 tuned, 1 full form, 2 split form
   bool split = false;   // form in use
+  bool pipe = false;    // row pipelining in use (FP32 full form)
+  int pipe_opt = 0;     // DBM_OPT_PIPELINE: 0 tuned, 1 off, 2 on
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
   int resident = 0, resident_split = 0;  // workgroups resident on the device, per form
@@ -273,13 +276,13 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->d_inst(), h->d_tiles(), nt, grid,
+      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles(), nt, grid,
                           in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
-        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->d_inst(), h->d_tiles() + b,
+        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles() + b,
                             nt, grid,
                             in_idx, fn_idx, out_idx, alpha, beta, st));
       }
@@ -354,7 +357,8 @@ int ensure_tuned(dbm_handle h) {
     tot += h->cells(k);
   }
   const TuneKey key{h->fp32 ? 1 : 0, h->S, h->lim, h->scheme,
-                    (int)std::lround(std::log2((double)tot + 1.0)), h->ninst, h->split_opt};
+                    (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
+                    h->split_opt * 3 + h->pipe_opt};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -376,18 +380,24 @@ int ensure_tuned(dbm_handle h) {
     for (int f = 0; f < 2; ++f) {
       if (!tune_form && f != form) continue;
       h->split = f == 1;
-      for (int r : cands) {
-        if (r > 2 * maxny && r > 1) break;
-        build_tiles(h, r);
-        int rc = upload_tiles(h);
-        if (rc) return rc;
-        double ms = 0.0;
-        if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
-        if ((rc = time_stage(h, 3, &ms))) return rc;
-        if (ms < best) {
-          best = ms;
-          best_rows = r;
-          best_form = f;
+      // the row pipeline exists for the FP32 full form
+      const bool can_pipe = h->fp32 && f == 0;
+      for (int pp = 0; pp < (can_pipe ? 2 : 1); ++pp) {
+        if ((h->pipe_opt == 1 && pp == 1) || (h->pipe_opt == 2 && can_pipe && pp == 0)) continue;
+        h->pipe = pp == 1;
+        for (int r : cands) {
+          if (r > 2 * maxny && r > 1) break;
+          build_tiles(h, r);
+          int rc = upload_tiles(h);
+          if (rc) return rc;
+          double ms = 0.0;
+          if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
+          if ((rc = time_stage(h, 3, &ms))) return rc;
+          if (ms < best) {
+            best = ms;
+            best_rows = r;
+            best_form = f + 2 * pp;
+          }
         }
       }
     }
@@ -396,8 +406,14 @@ int ensure_tuned(dbm_handle h) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = std::make_pair(want, form);
   }
-  if (want != h->rows || h->tiles.empty() || h->split != (form == 1)) {
-    h->split = form == 1;
+  if (h->tile_rows_opt > 0) {  // fixed rows: the form and pipeline the options ask for
+    form = h->split_opt == 2 ? 1 : 0;
+    if (form == 0 && h->fp32 && h->pipe_opt == 2) form = 2;
+  }
+  if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) == 1) ||
+      h->pipe != (form >= 2)) {
+    h->split = (form & 1) == 1;
+    h->pipe = form >= 2;
     build_tiles(h, want);
     int rc = upload_tiles(h);
     if (rc) return rc;
@@ -814,6 +830,12 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       h->rows = 0;
       h->tiles.clear();
       break;
+    case DBM_OPT_PIPELINE:
+      if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "pipeline must be 0, 1 or 2");
+      h->pipe_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
     default: return fail(DBM_ERR_ARG, "unknown or read-only option");
   }
   clear_graphs(h);
@@ -831,6 +853,7 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_GRAPH_CHUNK: *value = h->graph_chunk; break;
     case DBM_OPT_PERSISTENT: *value = h->grid_cap(); break;
     case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
+    case DBM_OPT_PIPELINE: *value = h->pipe ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;

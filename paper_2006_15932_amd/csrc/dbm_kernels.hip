@@ -611,17 +611,12 @@ static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) ==
 constexpr int kXPlanes = 12;
 constexpr int kHaloLanes = 3 * kXPlanes;
 
-// The per-cell chain (mixture u, T, chemistry) is the same for every
-// species of a cell: with DBM_SHARED_CHAIN one wavefront per row (rotating
-// with the row) computes it and publishes it through LDS while the others
-// advance their stencils; a second barrier per row precedes the collision.
-// Off by default: the second barrier and the longer live ranges (247 VGPRs
-// against 217) cost more than the S-fold chain saves (C4 2.34 ms against
-// 2.15 ms per launch).
-#ifndef DBM_SHARED_CHAIN
-#define DBM_SHARED_CHAIN 0
-#endif
-constexpr bool kSharedChain = DBM_SHARED_CHAIN;
+// Software pipeline over rows (PIPE, FP32): row k+1's moments, mixture
+// chain and collision are formed while row k's stencils are (their inputs
+// are already in registers: the prefetched row and the carried y-state),
+// which gives the scheduler two independent streams of work per row.  It
+// shortens each wavefront's rows (small, latency-bound grids gain) at 16
+// more VGPRs (large, throughput-bound grids lose); the tuner picks.
 
 // Halo distribution: LDS crossbar gather (1) or lane reads (0), per type.
 #ifndef DBM_GATHER_F32
@@ -635,11 +630,10 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
-template <typename T, int S, int LIM, bool RKC>
+template <typename T, int S, int LIM, bool RKC, bool PIPE>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
-                                           T alpha, T beta, double (*mom)[4 * S][kWave],
-                                           double (*cst)[3 + S][kWave]) {
+                                           T alpha, T beta, double (*mom)[4 * S][kWave]) {
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
   // One buffer resource per species and buffer (its 16 planes, under 4 GiB
@@ -716,6 +710,36 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     halo = bload<T>(rin, hoff + (uint32_t)(k * nx) * es, 0);
   };
 
+  // Collision of row k from its values fr: own FP64 moments to LDS, one
+  // barrier, the mixture chain from every species' moments, then the
+  // moment-space collision into dfo.
+  auto collide = [&](int k, const T *fr, SpC *sp, SpC &me, T *dfo) {
+    T oA[4], oB[4], oX[4], oY[4];
+    orbit_parts<T>(fr, oA, oB, oX, oY);
+    double n0, jx0, jy0, E0;
+    species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
+    double(*mb)[kWave] = mom[k & 1];
+    mb[0 * S + s][lane] = n0;
+    mb[1 * S + s][lane] = jx0;
+    mb[2 * S + s][lane] = jy0;
+    mb[3 * S + s][lane] = E0;
+    __syncthreads();
+    CellState cs;
+    cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
+    double dn_own = cs.dn[0];
+#pragma unroll
+    for (int q = 1; q < S; ++q)
+      if (q == s) dn_own = cs.dn[q];   // wave-uniform select, no indexed array
+    collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, cs.ux, cs.uy,
+                       cs.Tst, dfo);
+  };
+  constexpr bool kPipe = PIPE && sizeof(T) == 4;
+  T df[kNV];
+  if constexpr (kPipe) {
+    SpC *sp = launder(as_const(I.sp));
+    collide(y0, c, sp, sp[s], df);
+  }
+
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
   // values of row k+D-1, so D rows of loads are in flight.
   T ring[kPrefetch][kNV];
@@ -754,52 +778,27 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         cgy[g] = Tab<T>::cgy(me, g);
       }
     }
-    // Own species' FP64 moments to LDS; one barrier; everyone's back.
-    T oA[4], oB[4], oX[4], oY[4];
-    orbit_parts<T>(c, oA, oB, oX, oY);
-    double n0, jx0, jy0, E0;
-    species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
-    double(*mb)[kWave] = mom[k & 1];
-    mb[0 * S + s][lane] = n0;
-    mb[1 * S + s][lane] = jx0;
-    mb[2 * S + s][lane] = jy0;
-    mb[3 * S + s][lane] = E0;
-    __syncthreads();
-    // f^n of the Runge-Kutta combine, loaded here to shorten its live range
+    // Row k's collision: from the previous row (pipelined) or here.
+    if constexpr (!kPipe) collide(k, c, sp, me, df);
+    // Pipelined: row k+1's values are the prefetched row (v_y >= 0) or the
+    // carried next value (v_y < 0); form its collision now.
+    T dfn[kNV];
+    if constexpr (kPipe) {
+      if (k + 1 < yend) {
+        T fn1[kNV];
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) fn1[i] = plane_sy(i) < 0 ? y1[i] : cur[i];
+        collide(k + 1, fn1, sp, me, dfn);
+      }
+    }
+    // f^n of the Runge-Kutta combine
     T fnv[kNV];
     if constexpr (RKC) {
 #pragma unroll
       for (int i = 0; i < kNV; ++i) fnv[i] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, i * plb);
     }
-    // Mixture chain: computed here (every wavefront) or by the row's chain
-    // wavefront and published (shared).
-    double ux, uy, Tst, dn_own;
-    double(*cb)[kWave] = cst[k & 1];
-    if (!kSharedChain || s == k % S) {
-      CellState cs;
-      cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
-      ux = cs.ux;
-      uy = cs.uy;
-      Tst = cs.Tst;
-      dn_own = cs.dn[0];
-#pragma unroll
-      for (int q = 1; q < S; ++q)
-        if (q == s) dn_own = cs.dn[q];   // wave-uniform select, no indexed array
-      if constexpr (kSharedChain) {
-        cb[0][lane] = cs.ux;
-        cb[1][lane] = cs.uy;
-        cb[2][lane] = cs.Tst;
-#pragma unroll
-        for (int q = 0; q < S; ++q) cb[3 + q][lane] = cs.dn[q];
-      }
-    }
-    // Unshared chain: the collision first, then each plane's stencil is
-    // combined as it is formed.  Shared chain: the stencils first (while the
-    // chain wavefront works), the collision after the second barrier.
     const T om = Tab<T>::omega(me);
-    T df[kNV], acc[kNV], res[kNV];
-    if constexpr (!kSharedChain)
-      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, ux, uy, Tst, df);
+    T res[kNV];
     auto finish = [&](int i, T a) {
       res[i] = fma(om, df[i], a);
       // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
@@ -862,20 +861,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       } else {
         c[i] = fnew;
       }
-      if constexpr (kSharedChain)
-        acc[i] = a;
-      else
-        finish(i, a);
-    }
-    if constexpr (kSharedChain) {
-      __syncthreads();
-      ux = cb[0][lane];
-      uy = cb[1][lane];
-      Tst = cb[2][lane];
-      dn_own = cb[3 + s][lane];
-      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, ux, uy, Tst, df);
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) finish(i, acc[i]);
+      finish(i, a);
     }
     // FP32: one masked block of stores per row (lanes past nx hold wrapped
     // or clamped copies and write nothing), so that the row is one basic
@@ -885,6 +871,10 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 #pragma unroll
         for (int i = 0; i < kNV; ++i) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
       }
+    }
+    if constexpr (kPipe) {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) df[i] = dfn[i];
     }
   };
 
@@ -1155,19 +1145,18 @@ template <> struct Occ<double> { static constexpr int kMinWaves = DBM_MIN_WAVES_
 
 // One workgroup = S wavefronts, wavefront w advancing species w of a tile;
 // tiles are taken persistently from the table in XCD-grouped order.
-template <typename T, int S, int LIM, bool RKC>
+template <typename T, int S, int LIM, bool RKC, bool PIPE>
 __global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
                                                            const Tile *__restrict__ tiles,
                                                            int ntiles, int in_idx, int fn_idx,
                                                            int out_idx, T alpha, T beta,
                                                            int remap) {
   __shared__ double mom[2][4 * S][kWave];
-  __shared__ double cst[2][3 + S][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
-    fused_tile<T, S, LIM, RKC>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
-                               alpha, beta, mom, cst);
+    fused_tile<T, S, LIM, RKC, PIPE>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
+                               alpha, beta, mom);
     __syncthreads();
   }
 }
@@ -1733,6 +1722,7 @@ static int xcd_remap_flag() {
 }
 
 static bool g_split = false;  // set by launch_fused for the templates below
+static bool g_pipe = false;
 
 template <typename T, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
@@ -1742,9 +1732,13 @@ static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int nt
     hipLaunchKernelGGL((k_fused_split<T, S, LIM, RKC>), dim3(grid), dim3(kWave * 2 * S), 0, st,
                        insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
                        g_xcd_remap);
+  else if (g_pipe && sizeof(T) == 4)
+    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC, true>), dim3(grid), dim3(kWave * S), 0,
+                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+                       g_xcd_remap);
   else
-    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC>), dim3(grid), dim3(kWave * S), 0, st,
-                       insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC, false>), dim3(grid), dim3(kWave * S), 0,
+                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
                        g_xcd_remap);
   return hipGetLastError();
 }
@@ -1781,16 +1775,21 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
   }
 }
 
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, const InstDev *insts,
-                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
-                        int out_idx, double alpha, double beta, hipStream_t st) {
+hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, bool pipe,
+                        const InstDev *insts, const Tile *tiles, int ntiles, int grid,
+                        int in_idx, int fn_idx, int out_idx, double alpha, double beta,
+                        hipStream_t st) {
   xcd_remap_flag();
   g_split = split;
+  g_pipe = pipe;
   return fp32 ? launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
                                       out_idx, alpha, beta, st)
               : launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
                                        out_idx, alpha, beta, st);
 }
+
+template <typename T, int S, int LIM, bool RKC>
+constexpr auto k_fused_stage_np = k_fused_stage<T, S, LIM, RKC, false>;
 
 hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
   const void *fn = nullptr;
@@ -1801,7 +1800,7 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int 
            : (rkc ? (const void *)K<T, SS, DBM_LIM_NONE, true>                                 \
                   : (const void *)K<T, SS, DBM_LIM_NONE, false>)
 #define DBM_PICK(T, SS)                                                                         \
-  if (split) { DBM_PICK1(k_fused_split, T, SS); } else { DBM_PICK1(k_fused_stage, T, SS); }
+  if (split) { DBM_PICK1(k_fused_split, T, SS); } else { DBM_PICK1(k_fused_stage_np, T, SS); }
   if (fp32) {
     switch (S) { case 1: DBM_PICK(float, 1); break; case 2: DBM_PICK(float, 2); break;
                  case 3: DBM_PICK(float, 3); break; case 4: DBM_PICK(float, 4); break;

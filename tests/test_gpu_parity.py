@@ -338,3 +338,18 @@ def test_split_form_tile_shape_does_not_change_bits():
             ref = f
         else:
             np.testing.assert_array_equal(f, ref)
+
+
+@pytest.mark.parametrize("scheme", [W.EULER, W.RK3])
+def test_row_pipeline_fp32_within_1e5_and_equal_to_unpipelined(scheme):
+    """The FP32 row pipeline (row k+1's collision formed during row k) against
+    the oracle, and against the same run without it."""
+    p = W.reacting(n=70, ny=45, steps=300, precision="fp32", scheme=scheme)
+    on = gpu_run(p, 300, "fp32", tile_rows=4, options={D.DBM_OPT_PIPELINE: 2})
+    off = gpu_run(p, 300, "fp32", tile_rows=4, options={D.DBM_OPT_PIPELINE: 1})
+    assert on.get_option(D.DBM_OPT_PIPELINE) == 2 and off.get_option(D.DBM_OPT_PIPELINE) == 1
+    o, fo = oracle_run(p, 300)
+    errs = field_errors(p, on.moments(), o.moments(fo))
+    for k in ("rho", "u", "T"):
+        assert errs[k] < FP32_TOL, errs
+    assert f_error(on.get_f(), off.get_f()) < 1e-6
