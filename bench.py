@@ -41,8 +41,8 @@ UNIT = "cell-species updates/s"
 # workload, with the hash of the kernel source they were taken at.  A changed
 # kernel source makes the entry stale and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "c1/fp32": {"source": "5dc97c9d32d506fe", "bytes_per_launch": 26488852},
-    "c4/fp32": {"source": "5dc97c9d32d506fe", "bytes_per_launch": 10363545647},
+    "c1/fp32": {"source": "a1f8150b1d25f355", "bytes_per_launch": 26512762},
+    "c4/fp32": {"source": "a1f8150b1d25f355", "bytes_per_launch": 9920878410},
 }
 
 
@@ -73,13 +73,15 @@ def bytes_per_csu(precision: str, scheme: int) -> int:
     return es * (32 if scheme == 0 else 128)
 
 
-def gpu_run(p, precision, steps, warmup, tile_rows=0):
+def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0):
     import torch
     from paper_2006_15932_amd import dbm as D
     sim = D.Simulation(p, precision=precision)
     assert sim.get_option(D.DBM_OPT_PATH) == 0, "one-pass HIP path not active"
     if tile_rows:
         sim.set_option(D.DBM_OPT_TILE_ROWS, tile_rows)
+    if pipeline:
+        sim.set_option(D.DBM_OPT_PIPELINE, pipeline)
     sim.set_fields()
     sim.step(warmup)
     sim.synchronize()
@@ -92,6 +94,7 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0):
     launches = steps * (1 if p.scheme == 0 else 3)
     kern_ms = ms / launches
     rows = sim.get_option(D.DBM_OPT_TILE_ROWS)
+    sim.pipeline_in_use = sim.get_option(D.DBM_OPT_PIPELINE)
     return sim, ms, kern_ms, rows
 
 
@@ -197,7 +200,7 @@ def traffic_mode(args):
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs."""
     import torch
     p, _ = workload(args.workload, args.precision)
-    sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows)
+    sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows, args.pipeline)
     sim.time_stage_kernel(args.steps)
     sim.close()
     n = 256 << 20
@@ -219,6 +222,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--mode", default="bench", choices=["bench", "traffic"])
     ap.add_argument("--tile-rows", type=int, default=0, help="pin rows per tile (0 = autotune)")
+    ap.add_argument("--pipeline", type=int, default=0, choices=[0, 1, 2],
+                    help="FP32 row pipeline: 0 autotune, 1 off, 2 on (with --tile-rows)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
@@ -231,7 +236,9 @@ def main():
 
     p, desc = workload(args.workload, args.precision)
     assert p.scheme == 0, "one launch per step is assumed below"
-    sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows)
+    sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows,
+                                     args.pipeline)
+    pipeline = sim.pipeline_in_use
     csu_step = p.S * p.cells
     value = csu_step * args.steps / (ms * 1e-3)
     bpl = csu_step * bytes_per_csu(args.precision, p.scheme)
@@ -252,7 +259,7 @@ def main():
         "config": {"workload": desc, "grid": [p.nx, p.ny], "species": p.S,
                    "precision": "FP32-bulk (FP64 moments/T and conserved-row collision)"
                    if args.precision == "fp32" else "FP64", "scheme": "euler",
-                   "tile_rows": rows},
+                   "tile_rows": rows, "row_pipeline": pipeline == 2},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused_stage", "bytes_per_launch": bpl,
