@@ -51,7 +51,11 @@ enum {
   DBM_ERR_WORKSPACE = -6     /* workspace missing, misaligned or too small   */
 };
 
-enum { DBM_FP64 = 0, DBM_FP32_BULK = 1 };        /* storage / bulk arithmetic */
+/* Storage and bulk arithmetic of f: FP64; FP32-bulk (FP32 storage and bulk
+ * arithmetic, FP64 moments/T and conserved rows); FP32X (each value stored as
+ * FP32 plus the bfloat16 rounding of its remainder, about 32 significant bits
+ * in 6 bytes, with FP64 arithmetic). */
+enum { DBM_FP64 = 0, DBM_FP32_BULK = 1, DBM_FP32X = 2 };
 enum { DBM_EULER = 0, DBM_TVD_RK3 = 1 };         /* time scheme               */
 enum { DBM_LIM_MINMOD = 0, DBM_LIM_NONE = 1 };   /* NND limiter or unlimited  */
 enum { DBM_BC_PERIODIC = 0, DBM_BC_OUTFLOW = 1, DBM_BC_WALL = 2 };
@@ -99,7 +103,7 @@ typedef struct {
   const dbm_species *species;    /* nspecies entries                          */
   const dbm_reaction *reaction;  /* NULL = no chemistry                       */
   double accel[2];               /* external acceleration a (Eq.6)            */
-  int precision;                 /* DBM_FP64 | DBM_FP32_BULK                  */
+  int precision;                 /* DBM_FP64 | DBM_FP32_BULK | DBM_FP32X      */
   int time_scheme;               /* DBM_EULER | DBM_TVD_RK3                   */
   int limiter;                   /* DBM_LIM_MINMOD | DBM_LIM_NONE             */
   int force_T_mode;              /* temperature T_dagger of Eq.(6)            */

@@ -17,31 +17,33 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, bool pipe,
+hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe,
                         const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st);
-hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu);
-hipError_t launch_plain(bool fp32, const InstDev *insts, int inst, size_t cells, int S,
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu);
+hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
                         hipStream_t st);
-hipError_t launch_init(bool fp32, const InstDev *insts, int inst, size_t cells,
+hipError_t launch_init(int prec, const InstDev *insts, int inst, size_t cells,
                        const double *fields, int out_idx, hipStream_t st);
-hipError_t launch_moments(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_moments(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                           double *dst, hipStream_t st);
-hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_noneq(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int which, double *dst, hipStream_t st);
 int totals_blocks();
 int energy_rows();
-hipError_t launch_energy(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_energy(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                          int which, double *dst, hipStream_t st);
 hipError_t launch_rowsums(const double *src, int nrows, size_t cells, double area, double *part,
                           double *out, hipStream_t st);
-hipError_t launch_totals(bool fp32, const InstDev *insts, int inst, int in_idx, int nq,
+hipError_t launch_totals(int prec, const InstDev *insts, int inst, int in_idx, int nq,
                          double area, double *partials, double *out, hipStream_t st);
-hipError_t launch_widen(bool fp32, const void *src, double *dst, size_t n, hipStream_t st);
-hipError_t launch_narrow(bool fp32, const double *src, void *dst, size_t n, hipStream_t st);
-hipError_t launch_check(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_widen(int prec, const void *buf, size_t ntot, size_t first, double *dst,
+                        size_t n, hipStream_t st);
+hipError_t launch_narrow(int prec, const double *src, void *buf, size_t ntot, size_t first,
+                         size_t n, hipStream_t st);
+hipError_t launch_check(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int *flag, hipStream_t st);
 hipError_t launch_dpp_probe(int *out, hipStream_t st);
 hipError_t launch_delay(double microseconds, hipStream_t st);
@@ -96,7 +98,7 @@ int validate(const dbm_config *cfgs, int ninst) {
       return fail(DBM_ERR_ARG, who + "unknown boundary condition");
     if (c.nspecies < 1 || c.nspecies > kMaxSpecies || !c.species)
       return fail(DBM_ERR_ARG, who + "nspecies must be 1..16 with a species array");
-    if (c.precision < 0 || c.precision > 1 || c.time_scheme < 0 || c.time_scheme > 1 ||
+    if (c.precision < 0 || c.precision > 2 || c.time_scheme < 0 || c.time_scheme > 1 ||
         c.limiter < 0 || c.limiter > 1 || c.force_T_mode < 0 || c.force_T_mode > 1)
       return fail(DBM_ERR_ARG, who + "unknown precision, scheme, limiter or force mode");
     if (!std::isfinite(c.accel[0]) || !std::isfinite(c.accel[1]))
@@ -151,7 +153,12 @@ int validate(const dbm_config *cfgs, int ninst) {
   return DBM_OK;
 }
 
-size_t esize(const dbm_config &c) { return c.precision == DBM_FP32_BULK ? 4 : 8; }
+// Bytes per stored value (FP32X: 4-byte value + 2-byte residual) and per
+// value of the arithmetic type (plain-path scratch).
+size_t esize(const dbm_config &c) {
+  return c.precision == DBM_FP32_BULK ? 4 : (c.precision == DBM_FP32X ? 6 : 8);
+}
+size_t csize(const dbm_config &c) { return c.precision == DBM_FP32_BULK ? 4 : 8; }
 
 void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   const int S = cfgs[0].nspecies;
@@ -184,7 +191,7 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
       L.buf_off[b][k] = off;
       off = align_up(off + fbytes);
     }
-    size_t per_cell = std::max<size_t>((size_t)S * kNV * esize(cfgs[k]), 12 * sizeof(double));
+    size_t per_cell = std::max<size_t>((size_t)S * kNV * csize(cfgs[k]), 12 * sizeof(double));
     per_cell = std::max<size_t>(per_cell, (size_t)(S + 3) * sizeof(double));
     L.scratch_off[k] = off;
     off = align_up(off + per_cell * cells);
@@ -193,10 +200,10 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
 }
 
 struct TuneKey {
-  int fp32, S, lim, scheme, bucket, ninst, split_opt;
+  int prec, S, lim, scheme, bucket, ninst, split_opt;
   bool operator<(const TuneKey &o) const {
-    return std::tie(fp32, S, lim, scheme, bucket, ninst, split_opt) <
-           std::tie(o.fp32, o.S, o.lim, o.scheme, o.bucket, o.ninst, o.split_opt);
+    return std::tie(prec, S, lim, scheme, bucket, ninst, split_opt) <
+           std::tie(o.prec, o.S, o.lim, o.scheme, o.bucket, o.ninst, o.split_opt);
   }
 };
 std::mutex g_tune_mu;
@@ -208,7 +215,8 @@ int g_probe_state = 0;  // 0 unknown, 1 ok, -1 failed
 
 struct dbm_s {
   int ninst = 0, S = 0, scheme = 0, lim = 0;
-  bool fp32 = false;
+  bool fp32 = false;     // FP32-bulk
+  int prec = DBM_FP64;  // DBM_FP64 | DBM_FP32_BULK | DBM_FP32X
   std::vector<dbm_config> cfg;
   std::vector<std::vector<dbm_species>> species;
   std::vector<dbm_reaction> reaction;
@@ -276,20 +284,20 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles(), nt, grid,
+      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles(), nt, grid,
                           in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
-        HIPCHK(launch_fused(h->fp32, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles() + b,
+        HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles() + b,
                             nt, grid,
                             in_idx, fn_idx, out_idx, alpha, beta, st));
       }
     }
   } else {
     for (int k = 0; k < h->ninst; ++k)
-      HIPCHK(launch_plain(h->fp32, h->d_inst(), k, h->cells(k), h->S, in_idx, fn_idx, out_idx,
+      HIPCHK(launch_plain(h->prec, h->d_inst(), k, h->cells(k), h->S, in_idx, fn_idx, out_idx,
                           alpha, beta, rkc, st));
   }
   return DBM_OK;
@@ -356,7 +364,7 @@ int ensure_tuned(dbm_handle h) {
     maxny = std::max(maxny, h->cfg[k].ny);
     tot += h->cells(k);
   }
-  const TuneKey key{h->fp32 ? 1 : 0, h->S, h->lim, h->scheme,
+  const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
                     h->split_opt * 3 + h->pipe_opt};
   if (want <= 0) {
@@ -371,7 +379,7 @@ int ensure_tuned(dbm_handle h) {
     if (h->scheme == DBM_TVD_RK3) {  // give the timed stage realistic inputs
       for (int k = 0; k < h->ninst; ++k)
         HIPCHK(hipMemcpyAsync(h->inst[k].buf[1], h->inst[k].buf[0],
-                              (size_t)h->S * kNV * h->cells(k) * (h->fp32 ? 4 : 8),
+                              (size_t)h->S * kNV * h->cells(k) * esize(h->cfg[k]),
                               hipMemcpyDeviceToDevice, h->stream));
     }
     const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
@@ -454,7 +462,7 @@ int check_state(dbm_handle h) {
   int *flag = (int *)(h->ws + h->L.flag_off);
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), h->stream));
   for (int k = 0; k < h->ninst; ++k)
-    HIPCHK(launch_check(h->fp32, h->d_inst(), k, h->cells(k), h->cur, flag, h->stream));
+    HIPCHK(launch_check(h->prec, h->d_inst(), k, h->cells(k), h->cur, flag, h->stream));
   int hflag = 0;
   HIPCHK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -530,6 +538,7 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
   h->ninst = ninst;
   h->S = cfgs[0].nspecies;
   h->fp32 = cfgs[0].precision == DBM_FP32_BULK;
+  h->prec = cfgs[0].precision;
   h->scheme = cfgs[0].time_scheme;
   h->lim = cfgs[0].limiter;
   h->stream = (hipStream_t)hip_stream;
@@ -553,7 +562,8 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     h->cfg[k].chem = h->chem[k].empty() ? nullptr : h->chem[k].data();
     if (cfgs[k].bc_x == DBM_BC_WALL) h->fused_ok = false;
     // the one-pass kernel addresses one species' 16 planes with 32-bit offsets
-    if ((double)kNV * cfgs[k].nx * (double)cfgs[k].ny * (h->fp32 ? 4.0 : 8.0) >= 4294967296.0)
+    if ((double)kNV * cfgs[k].nx * (double)cfgs[k].ny * (h->prec == DBM_FP64 ? 8.0 : 4.0) >=
+        4294967296.0)
       h->fused_ok = false;
     InstDev d;
     std::memset(&d, 0, sizeof(d));
@@ -624,8 +634,8 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     int per_cu = 0, per_cu_split = 0, dev = 0;
     hipDeviceProp_t prop;
     const bool rk3 = h->scheme == DBM_TVD_RK3;
-    if ((e = fused_occupancy(h->fp32, h->S, h->lim, rk3, false, &per_cu)) != hipSuccess ||
-        (e = fused_occupancy(h->fp32, h->S, h->lim, rk3, true, &per_cu_split)) != hipSuccess ||
+    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, &per_cu)) != hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, &per_cu_split)) != hipSuccess ||
         (e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
       return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
@@ -659,7 +669,7 @@ int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
   HIPCHK(hipMemcpyAsync(stage + S * cells, ux, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(stage + (S + 1) * cells, uy, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(stage + (S + 2) * cells, T, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_init(h->fp32, h->d_inst(), inst, cells, stage, h->cur, h->stream));
+  HIPCHK(launch_init(h->prec, h->d_inst(), inst, cells, stage, h->cur, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DBM_OK;
 }
@@ -670,13 +680,13 @@ int dbm_set_f(dbm_handle h, int inst, const double *f) {
   if (!f) return fail(DBM_ERR_ARG, "NULL f");
   const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
   void *dst = h->inst[inst].buf[h->cur];
-  if (!h->fp32) {
+  if (h->prec == DBM_FP64) {
     HIPCHK(hipMemcpyAsync(dst, f, sizeof(double) * nplanes * cells, hipMemcpyHostToDevice, h->stream));
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
       HIPCHK(hipMemcpyAsync(stage, f + p * cells, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
-      HIPCHK(launch_narrow(true, stage, (float *)dst + p * cells, cells, h->stream));
+      HIPCHK(launch_narrow(h->prec, stage, dst, nplanes * cells, p * cells, cells, h->stream));
     }
   }
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -689,12 +699,12 @@ int dbm_get_f(dbm_handle h, int inst, double *f) {
   if (!f) return fail(DBM_ERR_ARG, "NULL f");
   const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
   const void *src = h->inst[inst].buf[h->cur];
-  if (!h->fp32) {
+  if (h->prec == DBM_FP64) {
     HIPCHK(hipMemcpyAsync(f, src, sizeof(double) * nplanes * cells, hipMemcpyDeviceToHost, h->stream));
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
-      HIPCHK(launch_widen(true, (const float *)src + p * cells, stage, cells, h->stream));
+      HIPCHK(launch_widen(h->prec, src, nplanes * cells, p * cells, stage, cells, h->stream));
       HIPCHK(hipMemcpyAsync(f + p * cells, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
     }
   }
@@ -741,7 +751,7 @@ int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, 
   if (rc) return rc;
   const size_t cells = h->cells(inst), S = h->S;
   double *stage = (double *)h->inst[inst].scratch;
-  HIPCHK(launch_moments(h->fp32, h->d_inst(), inst, cells, h->cur, stage, h->stream));
+  HIPCHK(launch_moments(h->prec, h->d_inst(), inst, cells, h->cur, stage, h->stream));
   if (rho_sp) HIPCHK(hipMemcpyAsync(rho_sp, stage, sizeof(double) * S * cells, hipMemcpyDeviceToHost, h->stream));
   if (ux) HIPCHK(hipMemcpyAsync(ux, stage + S * cells, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
   if (uy) HIPCHK(hipMemcpyAsync(uy, stage + (S + 1) * cells, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
@@ -757,7 +767,7 @@ int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals) {
   double *stage = (double *)h->inst[inst].scratch;
   if (delta) {
     for (int s = 0; s < h->S; ++s) {
-      HIPCHK(launch_noneq(h->fp32, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
+      HIPCHK(launch_noneq(h->prec, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
       HIPCHK(hipMemcpyAsync(delta + (size_t)s * 12 * cells, stage, sizeof(double) * 12 * cells,
                             hipMemcpyDeviceToHost, h->stream));
     }
@@ -765,7 +775,7 @@ int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals) {
   if (totals) {
     const int nq = h->S + 3;
     double *part = (double *)(h->ws + h->L.part_off), *tot = (double *)(h->ws + h->L.tot_off);
-    HIPCHK(launch_totals(h->fp32, h->d_inst(), inst, h->cur, nq,
+    HIPCHK(launch_totals(h->prec, h->d_inst(), inst, h->cur, nq,
                          h->cfg[inst].dx * h->cfg[inst].dy, part, tot, h->stream));
     HIPCHK(hipMemcpyAsync(totals, tot, sizeof(double) * nq, hipMemcpyDeviceToHost, h->stream));
   }
@@ -782,7 +792,7 @@ int dbm_energy_moments(dbm_handle h, int inst, double *fields, double *totals) {
   double *part = (double *)(h->ws + h->L.part_off), *tot = (double *)(h->ws + h->L.tot_off);
   const double area = h->cfg[inst].dx * h->cfg[inst].dy;
   for (int s = 0; s < h->S; ++s) {
-    HIPCHK(launch_energy(h->fp32, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
+    HIPCHK(launch_energy(h->prec, h->d_inst(), inst, cells, h->cur, s, stage, h->stream));
     if (fields)
       HIPCHK(hipMemcpyAsync(fields + (size_t)s * nr * cells, stage, sizeof(double) * nr * cells,
                             hipMemcpyDeviceToHost, h->stream));
@@ -826,6 +836,8 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       break;
     case DBM_OPT_SPLIT:
       if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "split must be 0, 1 or 2");
+      if (value == 2 && h->prec == DBM_FP32X)
+        return fail(DBM_ERR_UNSUPPORTED, "the split form has no FP32X storage variant");
       h->split_opt = value;
       h->rows = 0;
       h->tiles.clear();

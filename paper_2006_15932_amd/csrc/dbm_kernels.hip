@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <cstdlib>
 
 #include "../../include/dbm.h"
@@ -199,6 +200,119 @@ __device__ __forceinline__ double readlane(double v, int l) {
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
   return __hiloint2double(hi, lo);
 }
+
+// ---------------------------------------------------------------------------
+// Storage of f.  float (FP32-bulk) and double (FP64) hold each value itself.
+// f32x holds each value as its FP32 rounding plus the bfloat16 rounding of
+// the remainder (FP32's exponent range, 8 more significant bits: about 32 in
+// all, relative error <= 2^-32), in 6 bytes: a buffer of n values is n FP32
+// values followed by n 16-bit residuals.  f32x is read and written from FP64
+// arithmetic.
+// ---------------------------------------------------------------------------
+struct f32x {};
+template <typename ST> struct Stor;
+template <> struct Stor<float> { typedef float C; };
+template <> struct Stor<double> { typedef double C; };
+template <> struct Stor<f32x> { typedef double C; };
+template <typename ST> constexpr bool kSplitStore = std::is_same<ST, f32x>::value;
+
+__device__ __forceinline__ float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t bf16_round(float x) {  // to nearest, ties to even
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void split_f32x(double v, float &hi, uint16_t &lo) {
+  hi = (float)v;
+  lo = bf16_round((float)(v - (double)hi));   // v - hi is exact in FP64
+}
+__device__ __forceinline__ double join_f32x(float hi, uint16_t lo) {
+  return (double)hi + (double)bf16_value(lo);
+}
+
+// Element access to one buffer of n values (generic kernels).
+template <typename ST> struct FV {
+  typedef typename Stor<ST>::C C;
+  const void *b;
+  size_t n;
+  __device__ FV(const void *b_, size_t n_) : b(b_), n(n_) {}
+  __device__ C operator[](size_t i) const {
+    if constexpr (kSplitStore<ST>)
+      return join_f32x(((const float *)b)[i], ((const uint16_t *)((const float *)b + n))[i]);
+    else
+      return ((const ST *)b)[i];
+  }
+  __device__ void set(size_t i, C v) const {
+    if constexpr (kSplitStore<ST>) {
+      float hi;
+      uint16_t lo;
+      split_f32x(v, hi, lo);
+      ((float *)b)[i] = hi;
+      ((uint16_t *)((float *)b + n))[i] = lo;
+    } else {
+      ((ST *)b)[i] = (ST)v;
+    }
+  }
+};
+__device__ __forceinline__ size_t nvals(const InstDev &I) {
+  return (size_t)I.S * kNV * (size_t)I.nx * (size_t)I.ny;
+}
+template <typename ST> __device__ __forceinline__ FV<ST> fview(const InstDev &I, int b) {
+  return FV<ST>(I.buf[b], nvals(I));
+}
+
+// One species of one buffer as raw-buffer resources (one-pass kernel):
+// value(cell, plane) and store(cell, plane, v); the plane goes to the scalar
+// offset.  lane_value takes a per-lane plane (halo loads).
+template <typename ST> struct FBuf {
+  typedef typename Stor<ST>::C C;
+  static constexpr uint32_t es = kSplitStore<ST> ? 4 : sizeof(ST);
+  rsrc_t hi, lo;
+  uint32_t plb_hi, plb_lo;  // bytes per plane of each part
+  __device__ FBuf(const InstDev &I, int b, int s) {
+    const size_t plane = (size_t)I.nx * I.ny;
+    plb_hi = (uint32_t)plane * es;
+    plb_lo = (uint32_t)plane * 2u;
+    const size_t first = (size_t)s * kNV * plane;
+    if constexpr (kSplitStore<ST>) {
+      hi = make_rsrc((const float *)I.buf[b] + first, kNV * plb_hi);
+      lo = make_rsrc((const uint16_t *)((const float *)I.buf[b] + nvals(I)) + first, kNV * plb_lo);
+    } else {
+      hi = make_rsrc((const ST *)I.buf[b] + first, kNV * plb_hi);
+      lo = hi;
+    }
+  }
+  __device__ C value(uint32_t cell, uint32_t p) const {
+    if constexpr (kSplitStore<ST>) {
+      const float h = bload<float>(hi, cell * 4u, p * plb_hi);
+      const uint16_t l = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(lo, (int)(cell * 2u),
+                                                                       (int)(p * plb_lo), 0);
+      return join_f32x(h, l);
+    } else {
+      return bload<ST>(hi, cell * es, p * plb_hi);
+    }
+  }
+  __device__ C lane_value(uint32_t p, uint32_t cell) const {
+    if constexpr (kSplitStore<ST>) {
+      const float h = bload<float>(hi, p * plb_hi + cell * 4u, 0);
+      const uint16_t l = (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(lo, (int)(p * plb_lo + cell * 2u), 0, 0);
+      return join_f32x(h, l);
+    } else {
+      return bload<ST>(hi, p * plb_hi + cell * es, 0);
+    }
+  }
+  __device__ void store(uint32_t cell, uint32_t p, C v) const {
+    if constexpr (kSplitStore<ST>) {
+      float h;
+      uint16_t l;
+      split_f32x(v, h, l);
+      bstore(hi, h, cell * 4u, p * plb_hi);
+      __builtin_amdgcn_raw_buffer_store_b16(l, lo, (int)(cell * 2u), (int)(p * plb_lo), kStoreAux);
+    } else {
+      bstore(hi, v, cell * es, p * plb_hi);
+    }
+  }
+};
 
 // Lane gather through the LDS crossbar: lane l gets v from lane addr[l] / 4.
 __device__ __forceinline__ float bperm(int addr, float v) {
@@ -630,22 +744,18 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
-template <typename T, int S, int LIM, bool RKC, bool PIPE>
+template <typename ST, int S, int LIM, bool RKC, bool PIPE>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
-                                           T alpha, T beta, double (*mom)[4 * S][kWave]) {
+                                           typename Stor<ST>::C alpha,
+                                           double (*mom)[4 * S][kWave]) {
+  typedef typename Stor<ST>::C T;                  // arithmetic type
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
-  // One buffer resource per species and buffer (its 16 planes, under 4 GiB
-  // by a host check); offsets below it are 32-bit byte counts: the plane in
-  // the SGPR offset, the cell in the VGPR offset.
-  constexpr uint32_t es = sizeof(T);
-  const size_t plane = (size_t)nx * (size_t)ny;
-  const uint32_t plb = (uint32_t)plane * es;       // bytes per plane
-  const uint32_t spb = kNV * plb;                  // bytes per species
-  const rsrc_t rin = make_rsrc((const T *)I.buf[in_idx] + (size_t)s * kNV * plane, spb);
-  const rsrc_t rfn = make_rsrc((const T *)I.buf[fn_idx] + (size_t)s * kNV * plane, spb);
-  const rsrc_t rout = make_rsrc((const T *)I.buf[out_idx] + (size_t)s * kNV * plane, spb);
+  // One set of buffer resources per species and buffer (its 16 planes,
+  // under 4 GiB by a host check); offsets below them are 32-bit byte counts:
+  // the plane in the SGPR offset, the cell in the VGPR offset.
+  const FBuf<ST> bin(I, in_idx, s), bfn(I, fn_idx, s), bout(I, out_idx, s);
   const int col = x0 + lane;                       // column held by this lane
   const int lcol = map_x(col, nx, I.bcx);          // where its value lives
   const bool writer = col < nx;
@@ -653,18 +763,19 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 
   auto load = [&](int i, int roff, bool flip) -> T {
     const uint32_t p = flip ? mirror_y(i) : i;
-    return bload<T>(rin, (uint32_t)(roff + lcol) * es, p * plb);
+    return bin.value((uint32_t)(roff + lcol), p);
   };
   // Compact halo: lane 3j+w (j < 12) holds plane xplane(j) at column x0-1
   // (w = 0), x0-2 or x0+65 (w = 1, by the sign of v_x), x0+64 (w = 2).
   // Lanes 36..63 re-read lane 0's value (in bounds, never used).
-  uint32_t hoff;
+  uint32_t hplane, hcol;
   {
     const int hl = lane < kHaloLanes ? lane : 0;
     const int j = hl / 3, w = hl - 3 * j;
     const int hp = xplane(j);
-    const int hcol = w == 0 ? x0 - 1 : (w == 2 ? x0 + kWave : (plane_sx(hp) > 0 ? x0 - 2 : x0 + kWave + 1));
-    hoff = (uint32_t)hp * plb + (uint32_t)map_x(hcol, nx, I.bcx) * es;
+    const int hc = w == 0 ? x0 - 1 : (w == 2 ? x0 + kWave : (plane_sx(hp) > 0 ? x0 - 2 : x0 + kWave + 1));
+    hplane = (uint32_t)hp;
+    hcol = (uint32_t)map_x(hc, nx, I.bcx);
   }
   // Gather addresses of the halo: h1 puts slot 0 (x0-1) in lane 0 and slot 2
   // (x0+64) in lane 63; h2 broadcasts slot 1.  Plane j adds 12 j bytes.
@@ -707,7 +818,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     const int ra = map_y(k + 1, ny, bcy, fa) * nx, rb = map_y(k + 2, ny, bcy, fb) * nx;
 #pragma unroll
     for (int i = 0; i < kNV; ++i) dst[i] = plane_sy(i) < 0 ? load(i, rb, fb) : load(i, ra, fa);
-    halo = bload<T>(rin, hoff + (uint32_t)(k * nx) * es, 0);
+    halo = bin.lane_value(hplane, hcol + (uint32_t)(k * nx));
   };
 
   // Collision of row k from its values fr: own FP64 moments to LDS, one
@@ -795,7 +906,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     T fnv[kNV];
     if constexpr (RKC) {
 #pragma unroll
-      for (int i = 0; i < kNV; ++i) fnv[i] = bload<T>(rfn, (uint32_t)(rk + lcol) * es, i * plb);
+      for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rk + lcol), i);
     }
     const T om = Tab<T>::omega(me);
     T res[kNV];
@@ -805,7 +916,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       // the (small) stage difference
       if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
       if constexpr (!kEarlyHalo)
-        if (writer) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+        if (writer) bout.store((uint32_t)(rk + col), i, res[i]);
     };
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
@@ -869,7 +980,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     if constexpr (kEarlyHalo) {
       if (writer) {
 #pragma unroll
-        for (int i = 0; i < kNV; ++i) bstore(rout, res[i], (uint32_t)(rk + col) * es, i * plb);
+        for (int i = 0; i < kNV; ++i) bout.store((uint32_t)(rk + col), i, res[i]);
       }
     }
     if constexpr (kPipe) {
@@ -1142,21 +1253,23 @@ __device__ __forceinline__ void fused_tile_split(const InstDev &I, const int s, 
 template <typename T> struct Occ;
 template <> struct Occ<float> { static constexpr int kMinWaves = DBM_MIN_WAVES_F32; };
 template <> struct Occ<double> { static constexpr int kMinWaves = DBM_MIN_WAVES_F64; };
+template <> struct Occ<f32x> { static constexpr int kMinWaves = DBM_MIN_WAVES_F64; };
 
 // One workgroup = S wavefronts, wavefront w advancing species w of a tile;
 // tiles are taken persistently from the table in XCD-grouped order.
-template <typename T, int S, int LIM, bool RKC, bool PIPE>
-__global__ __launch_bounds__(kWave * S, Occ<T>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
+template <typename ST, int S, int LIM, bool RKC, bool PIPE>
+__global__ __launch_bounds__(kWave * S, Occ<ST>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
                                                            const Tile *__restrict__ tiles,
                                                            int ntiles, int in_idx, int fn_idx,
-                                                           int out_idx, T alpha, T beta,
+                                                           int out_idx,
+                                                           typename Stor<ST>::C alpha,
                                                            int remap) {
   __shared__ double mom[2][4 * S][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
-    fused_tile<T, S, LIM, RKC, PIPE>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx, out_idx,
-                               alpha, beta, mom);
+    fused_tile<ST, S, LIM, RKC, PIPE>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
+                                      out_idx, alpha, mom);
     __syncthreads();
   }
 }
@@ -1195,9 +1308,10 @@ __global__ __launch_bounds__(kWave * 2 * S, OccSplit<T>::kMinWaves) void k_fused
 // Plain path: one thread per cell for the equilibrium (dense FP64 M^{-1}),
 // one thread per (cell, plane) for convection + combine.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void plain_feq_cell(const InstDev &I, const T *f, size_t plane,
-                                               size_t cell, T *dst) {
+template <typename ST>
+__device__ __forceinline__ void plain_feq_cell(const InstDev &I, const FV<ST> &f, size_t plane,
+                                               size_t cell, typename Stor<ST>::C *dst) {
+  typedef typename Stor<ST>::C T;
   const int S = I.S;
   const SpeciesDev *sp = I.sp;
   double n[kMaxSpecies], jx[kMaxSpecies], jy[kMaxSpecies], E[kMaxSpecies];
@@ -1280,14 +1394,14 @@ __device__ __forceinline__ void plain_feq_cell(const InstDev &I, const T *f, siz
   }
 }
 
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_plain_eq(const InstDev *__restrict__ insts, int inst,
                                                   int in_idx) {
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
-  plain_feq_cell<T>(I, (const T *)I.buf[in_idx], plane, cell, (T *)I.scratch);
+  plain_feq_cell<ST>(I, fview<ST>(I, in_idx), plane, cell, (typename Stor<ST>::C *)I.scratch);
 }
 
 // Map a possibly-ghost index along one axis; walls reflect and flip.
@@ -1307,9 +1421,10 @@ __device__ __forceinline__ int map_axis(int j, int n, int bc, int &flips) {
   return q;
 }
 
-template <typename T>
-__device__ __forceinline__ T plain_value(const InstDev &I, const T *f, size_t plane, int s,
-                                         int i, int x, int y) {
+template <typename ST>
+__device__ __forceinline__ typename Stor<ST>::C plain_value(const InstDev &I, const FV<ST> &f,
+                                                            size_t plane, int s, int i, int x,
+                                                            int y) {
   int fx = 0, fy = 0;
   const int mx = map_axis(x, I.nx, I.bcx, fx), my = map_axis(y, I.ny, I.bcy, fy);
   int p = i;
@@ -1328,24 +1443,26 @@ __device__ __forceinline__ T nnd_face(T fm1, T f0, T fp1, T fp2, int sgn, int li
   return fp1 - T(0.5) * sl;
 }
 
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict__ insts,
                                                       int inst, int in_idx, int fn_idx,
-                                                      int out_idx, T alpha, T beta, int rkc) {
+                                                      int out_idx, typename Stor<ST>::C alpha,
+                                                      int rkc) {
+  typedef typename Stor<ST>::C T;
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
   const int si = blockIdx.y, s = si / kNV, i = si % kNV;
   const int x = (int)(cell % I.nx), y = (int)(cell / I.nx);
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   const SpeciesDev &sp = I.sp[s];
   const double vx = sp.M[1 * kNV + i], vy = sp.M[2 * kNV + i];
   const T fc = f[(size_t)si * plane + cell];
   T C = T(0);
   if (vx != 0.0) {
     T w[5];
-    for (int k = 0; k < 5; ++k) w[k] = plain_value<T>(I, f, plane, s, i, x - 2 + k, y);
+    for (int k = 0; k < 5; ++k) w[k] = plain_value<ST>(I, f, plane, s, i, x - 2 + k, y);
     const int sg = vx > 0 ? 1 : -1;
     const T fr = nnd_face<T>(w[1], w[2], w[3], w[4], sg, I.lim);
     const T fl = nnd_face<T>(w[0], w[1], w[2], w[3], sg, I.lim);
@@ -1353,7 +1470,7 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   }
   if (vy != 0.0) {
     T w[5];
-    for (int k = 0; k < 5; ++k) w[k] = plain_value<T>(I, f, plane, s, i, x, y - 2 + k);
+    for (int k = 0; k < 5; ++k) w[k] = plain_value<ST>(I, f, plane, s, i, x, y - 2 + k);
     const int sg = vy > 0 ? 1 : -1;
     const T fr = nnd_face<T>(w[1], w[2], w[3], w[4], sg, I.lim);
     const T fl = nnd_face<T>(w[0], w[1], w[2], w[3], sg, I.lim);
@@ -1361,15 +1478,15 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   }
   const T feq = ((const T *)I.scratch)[(size_t)si * plane + cell];
   T res = fc + C + (T)sp.omega * (feq - fc);
-  if (rkc) res = fma(alpha, ((const T *)I.buf[fn_idx])[(size_t)si * plane + cell] - res, res);
-  ((T *)I.buf[out_idx])[(size_t)si * plane + cell] = res;
+  if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - res, res);
+  fview<ST>(I, out_idx).set((size_t)si * plane + cell, res);
 }
 
 // ---------------------------------------------------------------------------
 // Initialisation, diagnostics, conversion
 // ---------------------------------------------------------------------------
 // f := f^eq(n^s, u, T); fields = [n_sp (S planes), ux, uy, T] in FP64.
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ insts, int inst,
                                                  const double *__restrict__ fields,
                                                  int out_idx) {
@@ -1380,7 +1497,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
   const int S = I.S;
   const double ux = fields[(size_t)S * plane + cell], uy = fields[(size_t)(S + 1) * plane + cell];
   const double Tm = fields[(size_t)(S + 2) * plane + cell];
-  T *out = (T *)I.buf[out_idx];
+  const FV<ST> out = fview<ST>(I, out_idx);
   for (int s = 0; s < S; ++s) {
     const SpeciesDev &sp = I.sp[s];
     const double nn = fields[(size_t)s * plane + cell], th = Tm * sp.inv_m, K = sp.K;
@@ -1405,14 +1522,14 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
     for (int r = 0; r < kNV; ++r) {
       double acc = 0.0;
       for (int k = 0; k < kNV; ++k) acc = fma(sp.Minv[r * kNV + k], h[k], acc);
-      out[(size_t)(s * kNV + r) * plane + cell] = (T)acc;
+      out.set((size_t)(s * kNV + r) * plane + cell, acc);
     }
   }
 }
 
 // Per-cell species moments in FP64 (dense rows of M).
-template <typename T>
-__device__ __forceinline__ void dense_moments(const InstDev &I, const T *f, size_t plane,
+template <typename ST>
+__device__ __forceinline__ void dense_moments(const InstDev &I, const FV<ST> &f, size_t plane,
                                               size_t cell, int s, double &n, double &jx,
                                               double &jy, double &E) {
   const SpeciesDev &sp = I.sp[s];
@@ -1427,18 +1544,18 @@ __device__ __forceinline__ void dense_moments(const InstDev &I, const T *f, size
 }
 
 // dst = [rho_sp (S planes), ux, uy, T]
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_moments(const InstDev *__restrict__ insts, int inst,
                                                  int in_idx, double *__restrict__ dst) {
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   double rho = 0, px = 0, py = 0, e = 0, kn = 0;
   for (int s = 0; s < I.S; ++s) {
     double n, jx, jy, E;
-    dense_moments<T>(I, f, plane, cell, s, n, jx, jy, E);
+    dense_moments<ST>(I, f, plane, cell, s, n, jx, jy, E);
     const double m = I.sp[s].m;
     dst[(size_t)s * plane + cell] = m * n;
     rho = fma(m, n, rho);
@@ -1454,7 +1571,7 @@ __global__ __launch_bounds__(256) void k_moments(const InstDev *__restrict__ ins
 }
 
 // Eqs.(17)-(20) for species `which`: dst = [12][cells].
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_noneq(const InstDev *__restrict__ insts, int inst,
                                                int in_idx, int which,
                                                double *__restrict__ dst) {
@@ -1462,11 +1579,11 @@ __global__ __launch_bounds__(256) void k_noneq(const InstDev *__restrict__ insts
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   double rho = 0, px = 0, py = 0, e = 0, kn = 0, nw = 0;
   for (int s = 0; s < I.S; ++s) {
     double n, jx, jy, E;
-    dense_moments<T>(I, f, plane, cell, s, n, jx, jy, E);
+    dense_moments<ST>(I, f, plane, cell, s, n, jx, jy, E);
     const double m = I.sp[s].m;
     if (s == which) nw = n;
     rho = fma(m, n, rho);
@@ -1525,7 +1642,7 @@ constexpr int kTotBlocks = 512;
 // v_ia; f^eq = f^eq(n^s, u, T) as for Delta.  Moments of f come from rows
 // v_x^2, v_y^2, q v_x, q v_y of M; those of f^eq are the closed forms of
 // fhat (M M^{-1} fhat = fhat).
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ insts, int inst,
                                                 int in_idx, int which,
                                                 double *__restrict__ dst) {
@@ -1533,11 +1650,11 @@ __global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ inst
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   double rho = 0, px = 0, py = 0, e = 0, kn = 0, nw = 0;
   for (int s = 0; s < I.S; ++s) {
     double n, jx, jy, E;
-    dense_moments<T>(I, f, plane, cell, s, n, jx, jy, E);
+    dense_moments<ST>(I, f, plane, cell, s, n, jx, jy, E);
     const double m = I.sp[s].m;
     if (s == which) nw = n;
     rho = fma(m, n, rho);
@@ -1573,13 +1690,13 @@ __global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ inst
 constexpr int kTotThreads = 256;
 
 // Partial totals per block: [block][S+3] = mass^s, Px, Py, E (unscaled).
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(kTotThreads) void k_totals_partial(const InstDev *__restrict__ insts,
                                                                 int inst, int in_idx,
                                                                 double *__restrict__ part) {
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   const int S = I.S, nq = S + 3;
   double acc[kMaxSpecies + 3];
   for (int q = 0; q < nq; ++q) acc[q] = 0.0;
@@ -1587,7 +1704,7 @@ __global__ __launch_bounds__(kTotThreads) void k_totals_partial(const InstDev *_
        cell += (size_t)gridDim.x * blockDim.x) {
     for (int s = 0; s < S; ++s) {
       double n, jx, jy, E;
-      dense_moments<T>(I, f, plane, cell, s, n, jx, jy, E);
+      dense_moments<ST>(I, f, plane, cell, s, n, jx, jy, E);
       const double m = I.sp[s].m;
       acc[s] = fma(m, n, acc[s]);
       acc[S] = fma(m, jx, acc[S]);
@@ -1644,28 +1761,30 @@ __global__ __launch_bounds__(64) void k_totals_final(const double *__restrict__ 
   out[q] = s * area;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_widen(const T *__restrict__ src, double *__restrict__ dst,
+template <typename ST>
+__global__ __launch_bounds__(256) void k_widen(const void *__restrict__ buf, size_t ntot,
+                                               size_t first, double *__restrict__ dst,
                                                size_t n) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[k] = (double)src[k];
+  if (k < n) dst[k] = (double)FV<ST>(buf, ntot)[first + k];
 }
-template <typename T>
-__global__ __launch_bounds__(256) void k_narrow(const double *__restrict__ src, T *__restrict__ dst,
-                                                size_t n) {
+template <typename ST>
+__global__ __launch_bounds__(256) void k_narrow(const double *__restrict__ src,
+                                                void *__restrict__ buf, size_t ntot,
+                                                size_t first, size_t n) {
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) dst[k] = (T)src[k];
+  if (k < n) FV<ST>(buf, ntot).set(first + k, (typename Stor<ST>::C)src[k]);
 }
 
 // Non-finite values, or a species density below -1e-12 of the local total.
-template <typename T>
+template <typename ST>
 __global__ __launch_bounds__(256) void k_check(const InstDev *__restrict__ insts, int inst,
                                                int in_idx, int *__restrict__ flag) {
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= plane) return;
-  const T *f = (const T *)I.buf[in_idx];
+  const FV<ST> f = fview<ST>(I, in_idx);
   double tot = 0.0, nmin = 0.0;
   bool bad = false;
   for (int s = 0; s < I.S; ++s) {
@@ -1724,75 +1843,95 @@ static int xcd_remap_flag() {
 static bool g_split = false;  // set by launch_fused for the templates below
 static bool g_pipe = false;
 
-template <typename T, int S, int LIM, bool RKC>
+template <typename ST, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                                  int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                                  hipStream_t st) {
-  if (g_split)
-    hipLaunchKernelGGL((k_fused_split<T, S, LIM, RKC>), dim3(grid), dim3(kWave * 2 * S), 0, st,
-                       insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
-                       g_xcd_remap);
-  else if (g_pipe && sizeof(T) == 4)
-    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC, true>), dim3(grid), dim3(kWave * S), 0,
-                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
-                       g_xcd_remap);
-  else
-    hipLaunchKernelGGL((k_fused_stage<T, S, LIM, RKC, false>), dim3(grid), dim3(kWave * S), 0,
-                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+  typedef typename Stor<ST>::C T;
+  if constexpr (!kSplitStore<ST>) {
+    if (g_split) {
+      hipLaunchKernelGGL((k_fused_split<ST, S, LIM, RKC>), dim3(grid), dim3(kWave * 2 * S), 0,
+                         st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
+                         g_xcd_remap);
+      return hipGetLastError();
+    }
+  }
+  bool piped = false;
+  if constexpr (std::is_same<ST, float>::value) {
+    if (g_pipe) {
+      hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, true>), dim3(grid), dim3(kWave * S), 0,
+                         st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha,
+                         g_xcd_remap);
+      piped = true;
+    }
+  }
+  if (!piped)
+    hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, false>), dim3(grid), dim3(kWave * S), 0,
+                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha,
                        g_xcd_remap);
   return hipGetLastError();
 }
 
-template <typename T, int S, int LIM>
+template <typename ST, int S, int LIM>
 static hipError_t launch_fused_s(bool rkc, const InstDev *insts, const Tile *tiles, int ntiles,
                                  int grid, int a, int b, int c, double al, double be,
                                  hipStream_t st) {
-  return rkc ? launch_fused_t<T, S, LIM, true>(insts, tiles, ntiles, grid, a, b, c, al, be, st)
-             : launch_fused_t<T, S, LIM, false>(insts, tiles, ntiles, grid, a, b, c, al, be, st);
+  return rkc ? launch_fused_t<ST, S, LIM, true>(insts, tiles, ntiles, grid, a, b, c, al, be, st)
+             : launch_fused_t<ST, S, LIM, false>(insts, tiles, ntiles, grid, a, b, c, al, be, st);
 }
 
-template <typename T, int S>
+template <typename ST, int S>
 static hipError_t launch_fused_l(int lim, bool rkc, const InstDev *insts, const Tile *tiles,
                                  int ntiles, int grid, int a, int b, int c, double al, double be,
                                  hipStream_t st) {
   return lim == DBM_LIM_MINMOD
-             ? launch_fused_s<T, S, DBM_LIM_MINMOD>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
-                                                    be, st)
-             : launch_fused_s<T, S, DBM_LIM_NONE>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
-                                                  be, st);
+             ? launch_fused_s<ST, S, DBM_LIM_MINMOD>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
+                                                     be, st)
+             : launch_fused_s<ST, S, DBM_LIM_NONE>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
+                                                   be, st);
 }
 
-template <typename T>
+template <typename ST>
 static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
                                  const Tile *tiles, int ntiles, int grid, int a, int b, int c,
                                  double al, double be, hipStream_t st) {
   switch (S) {
-    case 1: return launch_fused_l<T, 1>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 2: return launch_fused_l<T, 2>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 3: return launch_fused_l<T, 3>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 4: return launch_fused_l<T, 4>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
+    case 1: return launch_fused_l<ST, 1>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
+    case 2: return launch_fused_l<ST, 2>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
+    case 3: return launch_fused_l<ST, 3>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
+    case 4: return launch_fused_l<ST, 4>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_fused(bool fp32, int S, int lim, bool rkc, bool split, bool pipe,
+// prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
+hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe,
                         const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                         hipStream_t st) {
   xcd_remap_flag();
+  if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   g_split = split;
   g_pipe = pipe;
-  return fp32 ? launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
-                                      out_idx, alpha, beta, st)
-              : launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
-                                       out_idx, alpha, beta, st);
+  switch (prec) {
+    case DBM_FP32_BULK:
+      return launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
+                                   out_idx, alpha, beta, st);
+    case DBM_FP32X:
+      return launch_fused_p<f32x>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
+                                  out_idx, alpha, beta, st);
+    default:
+      return launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
+                                    out_idx, alpha, beta, st);
+  }
 }
 
-template <typename T, int S, int LIM, bool RKC>
-constexpr auto k_fused_stage_np = k_fused_stage<T, S, LIM, RKC, false>;
+template <typename ST, int S, int LIM, bool RKC>
+constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false>;
 
-hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
   const void *fn = nullptr;
+  if (prec == DBM_FP32X) split = false;  // full form only
 #define DBM_PICK1(K, T, SS)                                                                     \
   fn = lim == DBM_LIM_MINMOD                                                                   \
            ? (rkc ? (const void *)K<T, SS, DBM_LIM_MINMOD, true>                               \
@@ -1801,9 +1940,14 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int 
                   : (const void *)K<T, SS, DBM_LIM_NONE, false>)
 #define DBM_PICK(T, SS)                                                                         \
   if (split) { DBM_PICK1(k_fused_split, T, SS); } else { DBM_PICK1(k_fused_stage_np, T, SS); }
-  if (fp32) {
+#define DBM_PICKX(SS) DBM_PICK1(k_fused_stage_np, f32x, SS)
+  if (prec == DBM_FP32_BULK) {
     switch (S) { case 1: DBM_PICK(float, 1); break; case 2: DBM_PICK(float, 2); break;
                  case 3: DBM_PICK(float, 3); break; case 4: DBM_PICK(float, 4); break;
+                 default: return hipErrorInvalidValue; }
+  } else if (prec == DBM_FP32X) {
+    switch (S) { case 1: DBM_PICKX(1); break; case 2: DBM_PICKX(2); break;
+                 case 3: DBM_PICKX(3); break; case 4: DBM_PICKX(4); break;
                  default: return hipErrorInvalidValue; }
   } else {
     switch (S) { case 1: DBM_PICK(double, 1); break; case 2: DBM_PICK(double, 2); break;
@@ -1811,6 +1955,7 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int 
                  default: return hipErrorInvalidValue; }
   }
 #undef DBM_PICK
+#undef DBM_PICKX
 #undef DBM_PICK1
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S * (split ? 2 : 1),
                                                       0);
@@ -1818,51 +1963,54 @@ hipError_t fused_occupancy(bool fp32, int S, int lim, bool rkc, bool split, int 
 
 static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_plain(bool fp32, const InstDev *insts, int inst, size_t cells, int S,
+// Launch kernel template K for the storage type of `prec`.
+#define DBM_PREC_LAUNCH(prec, K, ...)                                                         \
+  do {                                                                                        \
+    switch (prec) {                                                                           \
+      case DBM_FP32_BULK: hipLaunchKernelGGL((K<float>), __VA_ARGS__); break;                 \
+      case DBM_FP32X: hipLaunchKernelGGL((K<f32x>), __VA_ARGS__); break;                      \
+      default: hipLaunchKernelGGL((K<double>), __VA_ARGS__); break;                           \
+    }                                                                                         \
+  } while (0)
+
+hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
                         hipStream_t st) {
+  (void)beta;  // alpha + beta = 1: the combine is res + alpha (f^n - res)
   const dim3 g1(blocks_for(cells, 256)), g2(blocks_for(cells, 256), (unsigned)(S * kNV));
-  if (fp32) {
+  if (prec == DBM_FP32_BULK) {
     hipLaunchKernelGGL(k_plain_eq<float>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<float>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
-                       out_idx, (float)alpha, (float)beta, (int)rkc);
+                       out_idx, (float)alpha, (int)rkc);
+  } else if (prec == DBM_FP32X) {
+    hipLaunchKernelGGL(k_plain_eq<f32x>, g1, dim3(256), 0, st, insts, inst, in_idx);
+    hipLaunchKernelGGL(k_plain_update<f32x>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
+                       out_idx, alpha, (int)rkc);
   } else {
     hipLaunchKernelGGL(k_plain_eq<double>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<double>, g2, dim3(256), 0, st, insts, inst, in_idx,
-                       fn_idx, out_idx, alpha, beta, (int)rkc);
+                       fn_idx, out_idx, alpha, (int)rkc);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_init(bool fp32, const InstDev *insts, int inst, size_t cells,
+hipError_t launch_init(int prec, const InstDev *insts, int inst, size_t cells,
                        const double *fields, int out_idx, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_init_eq<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
-                       inst, fields, out_idx);
-  else
-    hipLaunchKernelGGL(k_init_eq<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+  DBM_PREC_LAUNCH(prec, k_init_eq, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
                        inst, fields, out_idx);
   return hipGetLastError();
 }
 
-hipError_t launch_moments(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_moments(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                           double *dst, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_moments<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
-                       inst, in_idx, dst);
-  else
-    hipLaunchKernelGGL(k_moments<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+  DBM_PREC_LAUNCH(prec, k_moments, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
                        inst, in_idx, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_noneq(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int which, double *dst, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_noneq<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
-                       inst, in_idx, which, dst);
-  else
-    hipLaunchKernelGGL(k_noneq<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+  DBM_PREC_LAUNCH(prec, k_noneq, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
                        inst, in_idx, which, dst);
   return hipGetLastError();
 }
@@ -1870,13 +2018,9 @@ hipError_t launch_noneq(bool fp32, const InstDev *insts, int inst, size_t cells,
 int totals_blocks() { return kTotBlocks; }
 int energy_rows() { return kEnergyRows; }
 
-hipError_t launch_energy(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_energy(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                          int which, double *dst, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_energy<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
-                       inst, in_idx, which, dst);
-  else
-    hipLaunchKernelGGL(k_energy<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+  DBM_PREC_LAUNCH(prec, k_energy, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
                        inst, in_idx, which, dst);
   return hipGetLastError();
 }
@@ -1891,46 +2035,33 @@ hipError_t launch_rowsums(const double *src, int nrows, size_t cells, double are
   return hipGetLastError();
 }
 
-hipError_t launch_totals(bool fp32, const InstDev *insts, int inst, int in_idx, int nq,
+hipError_t launch_totals(int prec, const InstDev *insts, int inst, int in_idx, int nq,
                          double area, double *partials, double *out, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_totals_partial<float>, dim3(kTotBlocks), dim3(kTotThreads), 0, st,
-                       insts, inst, in_idx, partials);
-  else
-    hipLaunchKernelGGL(k_totals_partial<double>, dim3(kTotBlocks), dim3(kTotThreads), 0, st,
+  DBM_PREC_LAUNCH(prec, k_totals_partial, dim3(kTotBlocks), dim3(kTotThreads), 0, st,
                        insts, inst, in_idx, partials);
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partials, kTotBlocks, nq, area,
                      out);
   return hipGetLastError();
 }
 
-hipError_t launch_widen(bool fp32, const void *src, double *dst, size_t n, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_widen<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       (const float *)src, dst, n);
-  else
-    hipLaunchKernelGGL(k_widen<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st,
-                       (const double *)src, dst, n);
+// Values first .. first+n-1 of a buffer of ntot values <-> FP64.
+hipError_t launch_widen(int prec, const void *buf, size_t ntot, size_t first, double *dst,
+                        size_t n, hipStream_t st) {
+  DBM_PREC_LAUNCH(prec, k_widen, dim3(blocks_for(n, 256)), dim3(256), 0, st, buf, ntot, first,
+                  dst, n);
   return hipGetLastError();
 }
 
-hipError_t launch_narrow(bool fp32, const double *src, void *dst, size_t n, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_narrow<float>, dim3(blocks_for(n, 256)), dim3(256), 0, st, src,
-                       (float *)dst, n);
-  else
-    hipLaunchKernelGGL(k_narrow<double>, dim3(blocks_for(n, 256)), dim3(256), 0, st, src,
-                       (double *)dst, n);
+hipError_t launch_narrow(int prec, const double *src, void *buf, size_t ntot, size_t first,
+                         size_t n, hipStream_t st) {
+  DBM_PREC_LAUNCH(prec, k_narrow, dim3(blocks_for(n, 256)), dim3(256), 0, st, src, buf, ntot,
+                  first, n);
   return hipGetLastError();
 }
 
-hipError_t launch_check(bool fp32, const InstDev *insts, int inst, size_t cells, int in_idx,
+hipError_t launch_check(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int *flag, hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_check<float>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
-                       inst, in_idx, flag);
-  else
-    hipLaunchKernelGGL(k_check<double>, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
+  DBM_PREC_LAUNCH(prec, k_check, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
                        inst, in_idx, flag);
   return hipGetLastError();
 }

@@ -18,7 +18,8 @@ LIB_PATH = os.path.join(HERE, "libdbm.so")
 
 DBM_OK, DBM_ERR_ARG, DBM_ERR_SINGULAR_M, DBM_ERR_HIP = 0, -1, -2, -3
 DBM_ERR_NONFINITE, DBM_ERR_UNSUPPORTED, DBM_ERR_WORKSPACE = -4, -5, -6
-DBM_FP64, DBM_FP32_BULK = 0, 1
+DBM_FP64, DBM_FP32_BULK, DBM_FP32X = 0, 1, 2
+_PRECISIONS = {"fp64": DBM_FP64, "fp32": DBM_FP32_BULK, "fp32x": DBM_FP32X}
 DBM_EULER, DBM_TVD_RK3 = 0, 1
 DBM_LIM_MINMOD, DBM_LIM_NONE = 0, 1
 DBM_BC_PERIODIC, DBM_BC_OUTFLOW, DBM_BC_WALL = 0, 1, 2
@@ -156,7 +157,11 @@ class Configs:
                 self._keep.append(steps)
             c.accel[0], c.accel[1] = p.accel
             prec = precision if precision is not None else p.precision
-            c.precision = DBM_FP32_BULK if prec in ("fp32", DBM_FP32_BULK) else DBM_FP64
+            if isinstance(prec, str):
+                if prec not in _PRECISIONS:
+                    raise ValueError(f"unknown precision {prec!r}")
+                prec = _PRECISIONS[prec]
+            c.precision = int(prec)
             c.time_scheme, c.limiter, c.force_T_mode = p.scheme, p.limiter, p.force_T_mode
             self._keep.append(sp)
 
