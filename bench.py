@@ -73,11 +73,13 @@ def bytes_per_csu(precision: str, scheme: int) -> int:
     return es * (32 if scheme == 0 else 128)
 
 
-def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0):
+def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0):
     import torch
     from paper_2006_15932_amd import dbm as D
     sim = D.Simulation(p, precision=precision)
     assert sim.get_option(D.DBM_OPT_PATH) == 0, "one-pass HIP path not active"
+    if rounding:
+        sim.set_option(D.DBM_OPT_ROUNDING, rounding)
     if tile_rows:
         sim.set_option(D.DBM_OPT_TILE_ROWS, tile_rows)
     if pipeline:
@@ -224,6 +226,8 @@ def main():
     ap.add_argument("--tile-rows", type=int, default=0, help="pin rows per tile (0 = autotune)")
     ap.add_argument("--pipeline", type=int, default=0, choices=[0, 1, 2],
                     help="FP32 row pipeline: 0 autotune, 1 off, 2 on (with --tile-rows)")
+    ap.add_argument("--rounding", type=int, default=0, choices=[0, 1],
+                    help="FP32 stores: 0 round to nearest, 1 stochastic")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
@@ -237,7 +241,7 @@ def main():
     p, desc = workload(args.workload, args.precision)
     assert p.scheme == 0, "one launch per step is assumed below"
     sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows,
-                                     args.pipeline)
+                                     args.pipeline, args.rounding)
     pipeline = sim.pipeline_in_use
     csu_step = p.S * p.cells
     value = csu_step * args.steps / (ms * 1e-3)
@@ -259,7 +263,8 @@ def main():
         "config": {"workload": desc, "grid": [p.nx, p.ny], "species": p.S,
                    "precision": "FP32-bulk (FP64 moments/T and conserved-row collision)"
                    if args.precision == "fp32" else "FP64", "scheme": "euler",
-                   "tile_rows": rows, "row_pipeline": pipeline == 2},
+                   "tile_rows": rows, "row_pipeline": pipeline == 2,
+                   "rounding": "stochastic" if args.rounding else "nearest"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_fused_stage", "bytes_per_launch": bpl,
@@ -273,6 +278,10 @@ def main():
         s64, ms64, k64, _ = gpu_run(p64, "fp64", max(1, args.steps // 5), 20)
         extra["fp64_value"] = csu_step * max(1, args.steps // 5) / (ms64 * 1e-3)
         s64.close()
+        px, _ = workload(args.workload, "fp32x")
+        sx, msx, _, _ = gpu_run(px, "fp32x", max(1, args.steps // 5), 20)
+        extra["fp32x_value"] = csu_step * max(1, args.steps // 5) / (msx * 1e-3)
+        sx.close()
         extra["plain_fp64_value"] = plain_fp64(p)
         extra["speedup_fp32_fused_vs_plain_fp64"] = value / extra["plain_fp64_value"]
         extra["batched"] = batched()
@@ -297,6 +306,9 @@ def main():
                                          "frac": br / (kr * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                          "frac_of_achievable": br / (kr * 1e-3) / 1e9 / copy_gbs,
                                          "ms_per_launch": kr, "tile_rows": rr}}
+        sr.close()
+        sr, msr, kr, _ = gpu_run(pr, "fp32", 200, 10, rounding=1)
+        extra["rt_grid"]["value_stochastic_rounding"] = pr.S * pr.cells * 200 / (msr * 1e-3)
         sr.close()
         b = extra["batched"]
         b["persistent_hbm_frac"] = b["persistent"] * 128 / 1e9 / HBM_PEAK_GBS

@@ -188,10 +188,17 @@ enum {
                                1 one wavefront per species, 2 two wavefronts
                                per species, each holding 8 of the 16 planes;
                                get: 1 or 2 in use */
-  DBM_OPT_PIPELINE = 9      /* FP32 full form: row k+1's collision formed
+  DBM_OPT_PIPELINE = 9,     /* FP32 full form: row k+1's collision formed
                                while row k's stencils are; 0 tuned with the
                                tile rows (default; off when the rows are set),
                                1 off, 2 on; get: 1 or 2 in use */
+  DBM_OPT_ROUNDING = 10     /* FP32-bulk stores of f: 0 round to nearest
+                               (default), 1 stochastic rounding (unbiased:
+                               up or down with probabilities in proportion to
+                               the distances, 8 random bits per value hashed
+                               from the cell, species and state, so runs are
+                               deterministic); DBM_ERR_UNSUPPORTED for other
+                               precisions and with the split form */
 };
 int dbm_set_option(dbm_handle h, int option, int value);
 int dbm_get_option(dbm_handle h, int option, int *value);

@@ -17,14 +17,14 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
-hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe,
+hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
                         const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st);
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu);
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
-                        hipStream_t st);
+                        bool sr, hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *insts, int inst, size_t cells,
                        const double *fields, int out_idx, hipStream_t st);
 hipError_t launch_moments(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
@@ -217,6 +217,7 @@ struct dbm_s {
   int ninst = 0, S = 0, scheme = 0, lim = 0;
   bool fp32 = false;     // FP32-bulk
   int prec = DBM_FP64;  // DBM_FP64 | DBM_FP32_BULK | DBM_FP32X
+  int sr = 0;           // DBM_OPT_ROUNDING: 1 stochastic rounding of FP32 stores
   std::vector<dbm_config> cfg;
   std::vector<std::vector<dbm_species>> species;
   std::vector<dbm_reaction> reaction;
@@ -284,21 +285,21 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles(), nt, grid,
-                          in_idx, fn_idx, out_idx, alpha, beta, st));
+      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->d_inst(),
+                          h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
-        HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->d_inst(), h->d_tiles() + b,
-                            nt, grid,
-                            in_idx, fn_idx, out_idx, alpha, beta, st));
+        HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->d_inst(),
+                            h->d_tiles() + b, nt, grid, in_idx, fn_idx, out_idx, alpha, beta,
+                            st));
       }
     }
   } else {
     for (int k = 0; k < h->ninst; ++k)
       HIPCHK(launch_plain(h->prec, h->d_inst(), k, h->cells(k), h->S, in_idx, fn_idx, out_idx,
-                          alpha, beta, rkc, st));
+                          alpha, beta, rkc, h->sr != 0, st));
   }
   return DBM_OK;
 }
@@ -366,7 +367,7 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    h->split_opt * 3 + h->pipe_opt};
+                    (h->split_opt * 3 + h->pipe_opt) * 2 + h->sr};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -838,6 +839,8 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "split must be 0, 1 or 2");
       if (value == 2 && h->prec == DBM_FP32X)
         return fail(DBM_ERR_UNSUPPORTED, "the split form has no FP32X storage variant");
+      if (value == 2 && h->sr)
+        return fail(DBM_ERR_UNSUPPORTED, "the split form has no stochastic rounding");
       h->split_opt = value;
       h->rows = 0;
       h->tiles.clear();
@@ -845,6 +848,16 @@ int dbm_set_option(dbm_handle h, int option, int value) {
     case DBM_OPT_PIPELINE:
       if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "pipeline must be 0, 1 or 2");
       h->pipe_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
+    case DBM_OPT_ROUNDING:
+      if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "rounding must be 0 or 1");
+      if (value == 1 && h->prec != DBM_FP32_BULK)
+        return fail(DBM_ERR_UNSUPPORTED, "stochastic rounding applies to FP32-bulk storage");
+      if (value == 1 && h->split_opt == 2)
+        return fail(DBM_ERR_UNSUPPORTED, "the split form has no stochastic rounding");
+      h->sr = value;
       h->rows = 0;
       h->tiles.clear();
       break;
@@ -866,6 +879,7 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_PERSISTENT: *value = h->grid_cap(); break;
     case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
     case DBM_OPT_PIPELINE: *value = h->pipe ? 2 : 1; break;
+    case DBM_OPT_ROUNDING: *value = h->sr; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;

@@ -230,6 +230,33 @@ __device__ __forceinline__ double join_f32x(float hi, uint16_t lo) {
   return (double)hi + (double)bf16_value(lo);
 }
 
+// Stochastic rounding of FP32 stores (option of FP32-bulk).  Round-to-nearest
+// of f + d, repeated every step on slowly varying fields, makes the rounding
+// errors of successive steps alike and lets them add up; rounding up or down
+// with probabilities in proportion to the distances makes each store's
+// error zero in expectation, so they add up as a random walk instead.
+// The random bits are a hash of the cell, the species and the values being
+// updated (the state itself): results stay deterministic and do not depend on
+// tiling or launch order.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+// f + d rounded to FP32 stochastically with the 8 random bits in the low byte
+// of u8: the exact remainder of the nearest sum (exact when |f| >= |d|) plus
+// a dither uniform over 256 levels in (-ulp/2, ulp/2), rounded to nearest.
+__device__ __forceinline__ float sr_add(float f, float d, uint32_t u8) {
+  const float sm = f + d;
+  const float er = d - (sm - f);
+  const float ulp = __uint_as_float(__float_as_uint(sm) & 0x7f800000u) * 0x1p-23f;
+  const float u = (float)(u8 & 0xffu);
+  return sm + (er + fma(u, ulp * 0x1p-8f, ulp * (0x1p-9f - 0.5f)));
+}
+
 // Element access to one buffer of n values (generic kernels).
 template <typename ST> struct FV {
   typedef typename Stor<ST>::C C;
@@ -744,7 +771,7 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
-template <typename ST, int S, int LIM, bool RKC, bool PIPE>
+template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
                                            typename Stor<ST>::C alpha,
@@ -910,11 +937,31 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     }
     const T om = Tab<T>::omega(me);
     T res[kNV];
-    auto finish = [&](int i, T a) {
-      res[i] = fma(om, df[i], a);
-      // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds only
-      // the (small) stage difference
-      if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
+    // Stochastic rounding: the increment d is formed apart from f and the
+    // sum rounded once, with 8 random bits per value from four hashes per
+    // lane and row.
+    constexpr bool kSR = SR && std::is_same<ST, float>::value;
+    uint32_t rb[4];
+    if constexpr (kSR) {
+      uint32_t key = (uint32_t)(rk + col) * 0x9E3779B9u ^ (uint32_t)(s + 1) * 0x85EBCA6Bu;
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) key ^= __float_as_uint(c[i]) + (uint32_t)i * 0x27D4EB2Fu;
+      rb[0] = mix32(key);
+      rb[1] = mix32(rb[0] ^ 0x68E31DA4u);
+      rb[2] = mix32(rb[1] ^ 0xB5297A4Du);
+      rb[3] = mix32(rb[2] ^ 0x1B56C4E9u);
+    }
+    auto finish = [&](int i, T a, T f) {
+      if constexpr (kSR) {
+        T d = fma(om, df[i], a);
+        if constexpr (RKC) d = fma(alpha, (fnv[i] - f) - d, d);
+        res[i] = sr_add(f, d, rb[i >> 2] >> (8 * (i & 3)));
+      } else {
+        res[i] = fma(om, df[i], a);
+        // alpha + beta = 1 in every stage: res + alpha (f^n - res) rounds
+        // only the (small) stage difference
+        if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
+      }
       if constexpr (!kEarlyHalo)
         if (writer) bout.store((uint32_t)(rk + col), i, res[i]);
     };
@@ -922,7 +969,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     for (int i = 0; i < kNV; ++i) {
       const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
       const T f = c[i];
-      T a = f;
+      T a = kSR ? T(0) : f;   // with stochastic rounding: the increment alone
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
@@ -972,7 +1019,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       } else {
         c[i] = fnew;
       }
-      finish(i, a);
+      finish(i, a, f);
     }
     // FP32: one masked block of stores per row (lanes past nx hold wrapped
     // or clamped copies and write nothing), so that the row is one basic
@@ -1257,7 +1304,7 @@ template <> struct Occ<f32x> { static constexpr int kMinWaves = DBM_MIN_WAVES_F6
 
 // One workgroup = S wavefronts, wavefront w advancing species w of a tile;
 // tiles are taken persistently from the table in XCD-grouped order.
-template <typename ST, int S, int LIM, bool RKC, bool PIPE>
+template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR>
 __global__ __launch_bounds__(kWave * S, Occ<ST>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
                                                            const Tile *__restrict__ tiles,
                                                            int ntiles, int in_idx, int fn_idx,
@@ -1268,8 +1315,8 @@ __global__ __launch_bounds__(kWave * S, Occ<ST>::kMinWaves) void k_fused_stage(c
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
-    fused_tile<ST, S, LIM, RKC, PIPE>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
-                                      out_idx, alpha, mom);
+    fused_tile<ST, S, LIM, RKC, PIPE, SR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
+                                          out_idx, alpha, mom);
     __syncthreads();
   }
 }
@@ -1447,7 +1494,7 @@ template <typename ST>
 __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict__ insts,
                                                       int inst, int in_idx, int fn_idx,
                                                       int out_idx, typename Stor<ST>::C alpha,
-                                                      int rkc) {
+                                                      int rkc, int sr) {
   typedef typename Stor<ST>::C T;
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
@@ -1477,8 +1524,17 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
     C -= (T)(vy * I.dt / I.dy) * (fr - fl);
   }
   const T feq = ((const T *)I.scratch)[(size_t)si * plane + cell];
-  T res = fc + C + (T)sp.omega * (feq - fc);
-  if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - res, res);
+  T res;
+  if (std::is_same<ST, float>::value && sr) {   // stochastic rounding (see sr_add)
+    T d = C + (T)sp.omega * (feq - fc);
+    if (rkc) d = fma(alpha, (fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - fc) - d, d);
+    const uint32_t key = (uint32_t)cell * 0x9E3779B9u ^ (uint32_t)(si + 1) * 0x85EBCA6Bu ^
+                         (uint32_t)__float_as_uint((float)fc);
+    res = (T)sr_add((float)fc, (float)d, mix32(key));
+  } else {
+    res = fc + C + (T)sp.omega * (feq - fc);
+    if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - res, res);
+  }
   fview<ST>(I, out_idx).set((size_t)si * plane + cell, res);
 }
 
@@ -1842,6 +1898,7 @@ static int xcd_remap_flag() {
 
 static bool g_split = false;  // set by launch_fused for the templates below
 static bool g_pipe = false;
+static bool g_sr = false;
 
 template <typename ST, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
@@ -1856,19 +1913,19 @@ static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int nt
       return hipGetLastError();
     }
   }
-  bool piped = false;
+#define DBM_FUSED_LAUNCH(P, R)                                                                  \
+  hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R>), dim3(grid), dim3(kWave * S), 0, st,  \
+                     insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, g_xcd_remap)
   if constexpr (std::is_same<ST, float>::value) {
     if (g_pipe) {
-      hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, true>), dim3(grid), dim3(kWave * S), 0,
-                         st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha,
-                         g_xcd_remap);
-      piped = true;
+      if (g_sr) DBM_FUSED_LAUNCH(true, true); else DBM_FUSED_LAUNCH(true, false);
+    } else {
+      if (g_sr) DBM_FUSED_LAUNCH(false, true); else DBM_FUSED_LAUNCH(false, false);
     }
+  } else {
+    DBM_FUSED_LAUNCH(false, false);
   }
-  if (!piped)
-    hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, false>), dim3(grid), dim3(kWave * S), 0,
-                       st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha,
-                       g_xcd_remap);
+#undef DBM_FUSED_LAUNCH
   return hipGetLastError();
 }
 
@@ -1905,14 +1962,17 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
 }
 
 // prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
-hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe,
+// sr: stochastic rounding of the stores (FP32-bulk full form only).
+hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
                         const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                         hipStream_t st) {
   xcd_remap_flag();
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
+  if (sr && (prec != DBM_FP32_BULK || split)) return hipErrorInvalidValue;
   g_split = split;
   g_pipe = pipe;
+  g_sr = sr;
   switch (prec) {
     case DBM_FP32_BULK:
       return launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
@@ -1927,7 +1987,7 @@ hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pip
 }
 
 template <typename ST, int S, int LIM, bool RKC>
-constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false>;
+constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false, false>;
 
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
   const void *fn = nullptr;
@@ -1975,21 +2035,22 @@ static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n +
 
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
-                        hipStream_t st) {
+                        bool sr, hipStream_t st) {
+  if (sr && prec != DBM_FP32_BULK) return hipErrorInvalidValue;
   (void)beta;  // alpha + beta = 1: the combine is res + alpha (f^n - res)
   const dim3 g1(blocks_for(cells, 256)), g2(blocks_for(cells, 256), (unsigned)(S * kNV));
   if (prec == DBM_FP32_BULK) {
     hipLaunchKernelGGL(k_plain_eq<float>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<float>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
-                       out_idx, (float)alpha, (int)rkc);
+                       out_idx, (float)alpha, (int)rkc, (int)sr);
   } else if (prec == DBM_FP32X) {
     hipLaunchKernelGGL(k_plain_eq<f32x>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<f32x>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
-                       out_idx, alpha, (int)rkc);
+                       out_idx, alpha, (int)rkc, 0);
   } else {
     hipLaunchKernelGGL(k_plain_eq<double>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<double>, g2, dim3(256), 0, st, insts, inst, in_idx,
-                       fn_idx, out_idx, alpha, (int)rkc);
+                       fn_idx, out_idx, alpha, (int)rkc, 0);
   }
   return hipGetLastError();
 }

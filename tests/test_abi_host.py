@@ -130,3 +130,21 @@ def test_copy_rate_rejects_bad_arguments_before_any_launch(src, dst, nbytes, gri
     with pytest.raises(D.DbmError) as e:
         D.dbm_copy_rate(src, dst, nbytes, grid, reps, 0)
     assert e.value.code == D.DBM_ERR_ARG
+
+
+def test_binding_constants_match_the_header():
+    """Every DBM_* enumerator the binding names has the header's value."""
+    import re
+    hdr = open(os.path.join(ROOT, "include", "dbm.h")).read()
+    body = re.sub(r"/\*.*?\*/", "", hdr, flags=re.S)
+    vals = {}
+    for blk in re.findall(r"enum\s*\{(.*?)\}", body, flags=re.S):
+        for name, v in re.findall(r"(DBM_\w+)\s*=\s*(-?\d+)", blk):
+            vals[name] = int(v)
+    seen = 0
+    for name in dir(D):
+        if name.startswith("DBM_") and name in vals:
+            assert getattr(D, name) == vals[name], name
+            seen += 1
+    assert seen >= 20
+    assert D.DBM_OPT_ROUNDING == vals["DBM_OPT_ROUNDING"] == 10
