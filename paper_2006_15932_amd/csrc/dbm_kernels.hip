@@ -351,6 +351,18 @@ __device__ __forceinline__ double bperm(int addr, double v) {
   return __hiloint2double(hi, lo);
 }
 
+// A value entering the row-to-row state from the prefetch ring.  In FP64 it
+// is copied to a register of its own (a copy the compiler cannot fold away):
+// otherwise the state keeps the ring slot's registers, the next prefetch
+// into that slot lands elsewhere, and the copy back at the loop latch waits
+// for it, which drains the prefetch every other row.
+__device__ __forceinline__ float carry(float x) { return x; }
+__device__ __forceinline__ double carry(double x) {
+  double y;
+  asm volatile("v_mov_b64 %0, %1" : "=v"(y) : "v"(x));
+  return y;
+}
+
 // minmod(a, b) = median(a, b, 0): the smaller-magnitude argument when both
 // have the same sign, else 0.
 __device__ __forceinline__ float minmod(float a, float b) {
@@ -880,11 +892,19 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
 
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
   // values of row k+D-1, so D rows of loads are in flight.
+  // kSteady (FP64 arithmetic): the loop body has no conditional loads or
+  // rows, so the compiler's wait counts stay exact across the loop latch
+  // (with them it waits for every load in flight there).  Rows past the
+  // tile's end are then computed (from in-range rows: map_y wraps, clamps
+  // or mirrors every index) but not stored.  In FP32 the conditional form
+  // measured faster.
+  constexpr bool kSteady = sizeof(T) == 8;
   T ring[kPrefetch][kNV];
   T hring[kPrefetch];
   auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
-    if (k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
+    if (kSteady || k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
     const int rk = k * nx;
+    const int rkn = k < ny ? rk : (ny - 1) * nx;   // f^n row (a row past the grid: not stored)
     SpC *sp = launder(as_const(I.sp));
     SpC &me = sp[s];
     // Halo of the x-moving planes and the advection coefficients, fetched
@@ -933,7 +953,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     T fnv[kNV];
     if constexpr (RKC) {
 #pragma unroll
-      for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rk + lcol), i);
+      for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rkn + lcol), i);
     }
     const T om = Tab<T>::omega(me);
     T res[kNV];
@@ -963,7 +983,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
       }
       if constexpr (!kEarlyHalo)
-        if (writer) bout.store((uint32_t)(rk + col), i, res[i]);
+        if (writer && (!kSteady || k < yend)) bout.store((uint32_t)(rk + col), i, res[i]);
     };
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
@@ -1004,7 +1024,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T sk = slope_pos<LIM>(y1[i], dn);
         const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
         a = fma(-(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g)), Dy, a);
-        c[i] = fnew;
+        c[i] = carry(fnew);
         y1[i] = dn;
         y2[i] = sk;
       } else if (sy < 0) {
@@ -1014,10 +1034,10 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
         a = fma(kEarlyHalo ? cgy[g] : Tab<T>::cgy(me, g), Dy, a);
         c[i] = n1;
-        y1[i] = fnew;
+        y1[i] = carry(fnew);
         y2[i] = tk1;
       } else {
-        c[i] = fnew;
+        c[i] = carry(fnew);
       }
       finish(i, a, f);
     }
@@ -1042,7 +1062,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   for (int k = y0; k < yend; k += kPrefetch) {
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
-      if (k + d < yend)
+      if (kSteady || k + d < yend)
         row(k + d, ring[d], hring[d], ring[(d + kPrefetch - 1) % kPrefetch],
             hring[(d + kPrefetch - 1) % kPrefetch]);
     }
