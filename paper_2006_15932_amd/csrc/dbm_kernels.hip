@@ -824,31 +824,43 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   //   c  = f at the current row k
   //   y1 = f_k - f_{k-1}           (v_y > 0)   or f_{k+1}   (v_y < 0)
   //   y2 = slope at row k-1        (v_y > 0)   or slope at row k (v_y < 0)
-  T c[kNV], y1[kNV], y2[kNV];
+  // Row y0 is loaded first (the first collision needs only it), then the
+  // other rows of the stencil: y0-2, y0-1 (v_y > 0) or y0-1, y0+1 (v_y < 0).
+  T c[kNV], y1[kNV], y2[kNV], pa[kNV], pb[kNV];
   {
     bool fm2, fm1, f0, fp1;
     const int rm2 = map_y(y0 - 2, ny, bcy, fm2) * nx, rm1 = map_y(y0 - 1, ny, bcy, fm1) * nx;
     const int r0 = map_y(y0, ny, bcy, f0) * nx, rp1 = map_y(y0 + 1, ny, bcy, fp1) * nx;
 #pragma unroll
+    for (int i = 0; i < kNV; ++i) c[i] = load(i, r0, f0);
+#pragma unroll
     for (int i = 0; i < kNV; ++i) {
       const int sy = plane_sy(i);
       if (sy > 0) {
-        const T a = load(i, rm2, fm2), b = load(i, rm1, fm1), cc = load(i, r0, f0);
-        c[i] = cc;
-        y1[i] = cc - b;
-        y2[i] = slope_pos<LIM>(b - a, cc - b);
+        pa[i] = load(i, rm2, fm2);
+        pb[i] = load(i, rm1, fm1);
       } else if (sy < 0) {
-        const T a = load(i, rm1, fm1), cc = load(i, r0, f0), n1 = load(i, rp1, fp1);
-        c[i] = cc;
-        y1[i] = n1;
-        y2[i] = slope_neg<LIM>(cc - a, n1 - cc);
+        pa[i] = load(i, rm1, fm1);
+        pb[i] = load(i, rp1, fp1);
+      }
+    }
+  }
+  auto start_state = [&]() {
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) {
+      const int sy = plane_sy(i);
+      if (sy > 0) {
+        y1[i] = c[i] - pb[i];
+        y2[i] = slope_pos<LIM>(pb[i] - pa[i], c[i] - pb[i]);
+      } else if (sy < 0) {
+        y1[i] = pb[i];
+        y2[i] = slope_neg<LIM>(c[i] - pa[i], pb[i] - c[i]);
       } else {
-        c[i] = load(i, r0, f0);
         y1[i] = T(0);
         y2[i] = T(0);
       }
     }
-  }
+  };
 
   // New values consumed by row k: row k+1 (v_y >= 0) or k+2 (v_y < 0), and
   // the x-halo of row k itself (an interior row: no y mapping).
@@ -883,15 +895,22 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, cs.ux, cs.uy,
                        cs.Tst, dfo);
   };
+  // Row k consumes ring slot d and refills the slot freed by row k-1 with the
+  // values of row k+D-1, so D rows of loads are in flight.  (Issuing the
+  // first slots before the first collision measured slower than after it.)
+  T ring[kPrefetch][kNV];
+  T hring[kPrefetch];
   constexpr bool kPipe = PIPE && sizeof(T) == 4;
   T df[kNV];
-  if constexpr (kPipe) {
+  if constexpr (kPipe) {   // needs row y0 only: overlaps the other rows' loads
     SpC *sp = launder(as_const(I.sp));
     collide(y0, c, sp, sp[s], df);
   }
+  start_state();
+#pragma unroll
+  for (int d = 0; d < kPrefetch - 1; ++d)
+    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d]);
 
-  // Row k consumes ring slot d and refills the slot freed by row k-1 with the
-  // values of row k+D-1, so D rows of loads are in flight.
   // kSteady (FP64 arithmetic): the loop body has no conditional loads or
   // rows, so the compiler's wait counts stay exact across the loop latch
   // (with them it waits for every load in flight there).  Rows past the
@@ -899,8 +918,6 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   // or mirrors every index) but not stored.  In FP32 the conditional form
   // measured faster.
   constexpr bool kSteady = sizeof(T) == 8;
-  T ring[kPrefetch][kNV];
-  T hring[kPrefetch];
   auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
     if (kSteady || k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
     const int rk = k * nx;
@@ -1056,9 +1073,6 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     }
   };
 
-#pragma unroll
-  for (int d = 0; d < kPrefetch - 1; ++d)
-    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d]);
   for (int k = y0; k < yend; k += kPrefetch) {
 #pragma unroll
     for (int d = 0; d < kPrefetch; ++d) {
