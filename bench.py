@@ -101,8 +101,9 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0):
 
 
 def errors_vs_oracle(n=64, steps=200):
-    """FP32-bulk and FP64 runs of the same setup on an n x n instance against
-    the FP64 CPU oracle (relative L-infinity per field)."""
+    """FP32-bulk (round to nearest and stochastic rounding), FP32X and FP64
+    runs of the same setup on an n x n instance against the FP64 CPU oracle
+    (relative L-infinity per field)."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from gpu_helpers import field_errors, oracle_run
     from paper_2006_15932_amd import dbm as D
@@ -111,12 +112,15 @@ def errors_vs_oracle(n=64, steps=200):
     o, fo = oracle_run(p, steps)
     mo = o.moments(fo)
     out = {}
-    for prec in ("fp32", "fp64"):
+    for key, prec, rnd in (("fp32", "fp32", 0), ("fp32_stochastic_rounding", "fp32", 1),
+                           ("fp32x", "fp32x", 0), ("fp64", "fp64", 0)):
         sim = D.Simulation(p, precision=prec)
+        if rnd:
+            sim.set_option(D.DBM_OPT_ROUNDING, rnd)
         sim.set_fields()
         sim.step(steps)
         e = field_errors(p, sim.moments(), mo)
-        out[prec] = {k: float("%.3e" % v) for k, v in e.items()}
+        out[key] = {k: float("%.3e" % v) for k, v in e.items()}
         sim.close()
     return out
 
