@@ -128,7 +128,11 @@ size_t dbm_workspace_bytes(const dbm_config *cfgs, int ninst);
  * negative I), DBM_ERR_SINGULAR_M, DBM_ERR_UNSUPPORTED (reaction with unequal
  * tau across species, or mixed template parameters in a batch),
  * DBM_ERR_WORKSPACE (NULL, unaligned to 256 bytes, or ws_bytes too small),
- * DBM_ERR_HIP. */
+ * DBM_ERR_HIP.
+ * Path: the one-pass stage kernels serve nspecies <= 4 with periodic or
+ * outflow x boundaries and under 4 GiB per species and buffer (16 planes in
+ * the storage type, FP32 part for FP32X); any other configuration runs the
+ * plain kernels (DBM_OPT_PATH reads 1), with the same results to rounding. */
 int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_workspace,
                size_t ws_bytes, dbm_handle *out);
 
