@@ -1,0 +1,52 @@
+"""FP32 storage variants against the FP64 oracle at the step counts the
+workloads are stated with, on sizes the oracle runs in seconds.
+
+- The Rayleigh-Taylor setup (20000 steps, FP32): round-to-nearest storage
+  drifts; stochastic rounding of the stores keeps it within 1e-5.
+- The batch's fast-reacting 128^2 instances (2000 steps): any storage
+  rounding is amplified about 10^3 there, so FP32 storage does not meet
+  1e-5 in either rounding mode; FP32X storage does.
+The round-to-nearest errors are printed for the record, not asserted.
+"""
+import pytest
+
+from gpu_helpers import field_errors, gpu_run, oracle_run
+from paper_2006_15932_amd import dbm as D
+from paper_2006_15932_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def _oracle(p, steps):
+    o, fo = oracle_run(p, steps, threads=16)
+    return o.moments(fo)
+
+
+def _errs(p, steps, precision, mo, **kw):
+    sim = gpu_run(p, steps, precision, **kw)
+    e = field_errors(p, sim.moments(), mo)
+    print(p.name, p.nx, precision, kw, "steps", steps,
+          {k: float("%.3e" % e[k]) for k in ("rho", "u", "T")}, flush=True)
+    return e
+
+
+def test_rayleigh_taylor_20000_steps_stochastic_rounding_within_1e5():
+    p = W.rayleigh_taylor(n=64, steps=20000, precision="fp32")
+    mo = _oracle(p, 20000)
+    e = _errs(p, 20000, "fp32", mo, options={D.DBM_OPT_ROUNDING: 1})
+    for k in ("rho", "u", "T"):
+        assert e[k] < TOL, (k, e)
+    _errs(p, 20000, "fp32", mo)
+
+
+@pytest.mark.parametrize("k", [48, 56])
+def test_batch_instance_2000_steps_fp32x_within_1e5(k):
+    p = W.batch(count=64, steps=2000, precision="fp32x")[k]
+    assert p.nx == 128
+    mo = _oracle(p, 2000)
+    e = _errs(p, 2000, "fp32x", mo)
+    for key in ("rho", "u", "T"):
+        assert e[key] < TOL, (key, e)
+    _errs(p, 2000, "fp32", mo)
