@@ -148,3 +148,22 @@ def test_binding_constants_match_the_header():
             seen += 1
     assert seen >= 20
     assert D.DBM_OPT_ROUNDING == vals["DBM_OPT_ROUNDING"] == 10
+
+
+def test_plain_c_consumer_builds_links_and_runs(tmp_path):
+    """The header compiles as strict C99 and the library links and runs
+    from C (host-only entry points; no GPU)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lib_dir = os.path.dirname(D.LIB_PATH)
+    exe = str(tmp_path / "abi_consumer")
+    cmd = [cc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror",
+           "-I", os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "abi_consumer.c"),
+           "-o", exe, "-L", lib_dir, "-ldbm", "-Wl,-rpath," + lib_dir]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and r.stdout.startswith("OK"), (r.stdout, r.stderr)
