@@ -1920,41 +1920,45 @@ __global__ __launch_bounds__(64) void k_delay(unsigned long long ticks) {
 // Host-side launchers (called from dbm_api.cpp)
 // ---------------------------------------------------------------------------
 // Tile order: XCD-grouped (1, default) or plain dispatch order (0, for
-// comparison; DBM_XCD_REMAP=0 in the environment).
-static int g_xcd_remap = -1;
+// comparison; DBM_XCD_REMAP=0 in the environment), read once per process.
 static int xcd_remap_flag() {
-  if (g_xcd_remap < 0) {
+  static const int flag = [] {
     const char *e = getenv("DBM_XCD_REMAP");
-    g_xcd_remap = (e && e[0] == '0') ? 0 : 1;
-  }
-  return g_xcd_remap;
+    return (e && e[0] == '0') ? 0 : 1;
+  }();
+  return flag;
 }
 
-static bool g_split = false;  // set by launch_fused for the templates below
-static bool g_pipe = false;
-static bool g_sr = false;
+// One launch of the stage kernel: its arguments and the kernel variant.
+struct FusedLaunch {
+  const InstDev *insts;
+  const Tile *tiles;
+  int ntiles, grid, in_idx, fn_idx, out_idx, remap;
+  double alpha, beta;
+  bool split, pipe, sr;  // split form, row pipeline, stochastic rounding
+  hipStream_t st;
+};
 
 template <typename ST, int S, int LIM, bool RKC>
-static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int ntiles, int grid,
-                                 int in_idx, int fn_idx, int out_idx, double alpha, double beta,
-                                 hipStream_t st) {
+static hipError_t launch_fused_t(const FusedLaunch &a) {
   typedef typename Stor<ST>::C T;
   if constexpr (!kSplitStore<ST>) {
-    if (g_split) {
-      hipLaunchKernelGGL((k_fused_split<ST, S, LIM, RKC>), dim3(grid), dim3(kWave * 2 * S), 0,
-                         st, insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, (T)beta,
-                         g_xcd_remap);
+    if (a.split) {
+      hipLaunchKernelGGL((k_fused_split<ST, S, LIM, RKC>), dim3(a.grid), dim3(kWave * 2 * S), 0,
+                         a.st, a.insts, a.tiles, a.ntiles, a.in_idx, a.fn_idx, a.out_idx,
+                         (T)a.alpha, (T)a.beta, a.remap);
       return hipGetLastError();
     }
   }
 #define DBM_FUSED_LAUNCH(P, R)                                                                  \
-  hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R>), dim3(grid), dim3(kWave * S), 0, st,  \
-                     insts, tiles, ntiles, in_idx, fn_idx, out_idx, (T)alpha, g_xcd_remap)
+  hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R>), dim3(a.grid), dim3(kWave * S), 0,    \
+                     a.st, a.insts, a.tiles, a.ntiles, a.in_idx, a.fn_idx, a.out_idx,           \
+                     (T)a.alpha, a.remap)
   if constexpr (std::is_same<ST, float>::value) {
-    if (g_pipe) {
-      if (g_sr) DBM_FUSED_LAUNCH(true, true); else DBM_FUSED_LAUNCH(true, false);
+    if (a.pipe) {
+      if (a.sr) DBM_FUSED_LAUNCH(true, true); else DBM_FUSED_LAUNCH(true, false);
     } else {
-      if (g_sr) DBM_FUSED_LAUNCH(false, true); else DBM_FUSED_LAUNCH(false, false);
+      if (a.sr) DBM_FUSED_LAUNCH(false, true); else DBM_FUSED_LAUNCH(false, false);
     }
   } else {
     DBM_FUSED_LAUNCH(false, false);
@@ -1964,33 +1968,23 @@ static hipError_t launch_fused_t(const InstDev *insts, const Tile *tiles, int nt
 }
 
 template <typename ST, int S, int LIM>
-static hipError_t launch_fused_s(bool rkc, const InstDev *insts, const Tile *tiles, int ntiles,
-                                 int grid, int a, int b, int c, double al, double be,
-                                 hipStream_t st) {
-  return rkc ? launch_fused_t<ST, S, LIM, true>(insts, tiles, ntiles, grid, a, b, c, al, be, st)
-             : launch_fused_t<ST, S, LIM, false>(insts, tiles, ntiles, grid, a, b, c, al, be, st);
+static hipError_t launch_fused_s(bool rkc, const FusedLaunch &a) {
+  return rkc ? launch_fused_t<ST, S, LIM, true>(a) : launch_fused_t<ST, S, LIM, false>(a);
 }
 
 template <typename ST, int S>
-static hipError_t launch_fused_l(int lim, bool rkc, const InstDev *insts, const Tile *tiles,
-                                 int ntiles, int grid, int a, int b, int c, double al, double be,
-                                 hipStream_t st) {
-  return lim == DBM_LIM_MINMOD
-             ? launch_fused_s<ST, S, DBM_LIM_MINMOD>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
-                                                     be, st)
-             : launch_fused_s<ST, S, DBM_LIM_NONE>(rkc, insts, tiles, ntiles, grid, a, b, c, al,
-                                                   be, st);
+static hipError_t launch_fused_l(int lim, bool rkc, const FusedLaunch &a) {
+  return lim == DBM_LIM_MINMOD ? launch_fused_s<ST, S, DBM_LIM_MINMOD>(rkc, a)
+                               : launch_fused_s<ST, S, DBM_LIM_NONE>(rkc, a);
 }
 
 template <typename ST>
-static hipError_t launch_fused_p(int S, int lim, bool rkc, const InstDev *insts,
-                                 const Tile *tiles, int ntiles, int grid, int a, int b, int c,
-                                 double al, double be, hipStream_t st) {
+static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a) {
   switch (S) {
-    case 1: return launch_fused_l<ST, 1>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 2: return launch_fused_l<ST, 2>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 3: return launch_fused_l<ST, 3>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
-    case 4: return launch_fused_l<ST, 4>(lim, rkc, insts, tiles, ntiles, grid, a, b, c, al, be, st);
+    case 1: return launch_fused_l<ST, 1>(lim, rkc, a);
+    case 2: return launch_fused_l<ST, 2>(lim, rkc, a);
+    case 3: return launch_fused_l<ST, 3>(lim, rkc, a);
+    case 4: return launch_fused_l<ST, 4>(lim, rkc, a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -2001,22 +1995,14 @@ hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pip
                         const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                         hipStream_t st) {
-  xcd_remap_flag();
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   if (sr && (prec != DBM_FP32_BULK || split)) return hipErrorInvalidValue;
-  g_split = split;
-  g_pipe = pipe;
-  g_sr = sr;
+  const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
+                      alpha, beta, split, pipe, sr, st};
   switch (prec) {
-    case DBM_FP32_BULK:
-      return launch_fused_p<float>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
-                                   out_idx, alpha, beta, st);
-    case DBM_FP32X:
-      return launch_fused_p<f32x>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
-                                  out_idx, alpha, beta, st);
-    default:
-      return launch_fused_p<double>(S, lim, rkc, insts, tiles, ntiles, grid, in_idx, fn_idx,
-                                    out_idx, alpha, beta, st);
+    case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
+    case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);
+    default: return launch_fused_p<double>(S, lim, rkc, a);
   }
 }
 
