@@ -331,7 +331,16 @@ int time_stage(dbm_handle h, int reps, double *ms) {
   // Fill the queue behind a short delay kernel so that back-to-back launches
   // are timed, not the host's submission rate.
   HIPCHK(launch_delay(50.0 + 25.0 * reps, h->stream));
-  std::vector<hipEvent_t> ev(2 * reps);
+  // events released on every return path
+  struct Events {
+    std::vector<hipEvent_t> v;
+    ~Events() {
+      for (auto e : v)
+        if (e) hipEventDestroy(e);
+    }
+  } evs;
+  evs.v.assign(2 * reps, nullptr);
+  std::vector<hipEvent_t> &ev = evs.v;
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   int rc = DBM_OK;
   for (int r = 0; r < reps && !rc; ++r) {
@@ -346,7 +355,6 @@ int time_stage(dbm_handle h, int reps, double *ms) {
     HIPCHK(hipEventElapsedTime(&t, ev[2 * r], ev[2 * r + 1]));
     tot += t;
   }
-  for (auto &e : ev) hipEventDestroy(e);
   if (rc) return rc;
   *ms = tot / reps;
   return DBM_OK;
