@@ -186,7 +186,7 @@ enum {
   DBM_OPT_CHECK_EVERY = 4,  /* non-finite check every K steps; 0 = off         */
   DBM_OPT_BATCH_MODE = 5,   /* 0 one launch per stage for all instances,
                                1 one launch per instance (comparison mode)     */
-  DBM_OPT_GRAPH_CHUNK = 6,  /* steps captured per graph (default 16)          */
+  DBM_OPT_GRAPH_CHUNK = 6,  /* steps captured per graph (default 256)         */
   DBM_OPT_PERSISTENT = 7,   /* read only: resident workgroups of a launch      */
   DBM_OPT_SPLIT = 8,        /* form of the one-pass kernel: 0 default (= 1),
                                1 one wavefront per species, 2 two wavefronts

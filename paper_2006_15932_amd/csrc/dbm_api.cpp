@@ -228,7 +228,7 @@ struct dbm_s {
   std::vector<InstDev> inst;
   int cur = 0;
   int path = 0, use_graph = 1, tile_rows_opt = 0, check_every = 0, batch_mode = 0,
-      graph_chunk = 16;
+      graph_chunk = 256;
   bool fused_ok = false;
   int rows = 0;  // rows per tile in use (0 = not tuned yet)
   int split_opt = 0;    // DBM_OPT_SPLIT: 0 tuned, 1 full form, 2 split form
