@@ -123,3 +123,18 @@ def test_fp32x_split_form_is_rejected():
     sim = D.Simulation(p, precision="fp32x")
     with pytest.raises(Exception):
         sim.set_option(D.DBM_OPT_SPLIT, 2)
+
+
+@pytest.mark.parametrize("nx,ny", [(1, 9), (7, 1), (3, 2), (60, 5), (65, 3)])
+@pytest.mark.parametrize("precision,opts,tol", [("fp32x", {}, FP32X_TOL),
+                                                ("fp32", {}, 1e-5),
+                                                ("fp32", {D.DBM_OPT_ROUNDING: 1}, 1e-5)])
+def test_degenerate_sizes_narrow_storage(nx, ny, precision, opts, tol):
+    """Grids narrower or shorter than the stencil (periodic wrap onto the
+    same cells, one-row tiles) in the narrow storage modes."""
+    p = W.reacting(n=nx, ny=ny, steps=1, precision=precision)
+    sim = gpu_run(p, 12, precision, options=opts)
+    o, fo = oracle_run(p, 12)
+    errs = field_errors(p, sim.moments(), o.moments(fo))
+    for k in ("rho", "u", "T"):
+        assert errs[k] < tol, (k, errs)
