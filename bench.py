@@ -190,15 +190,35 @@ def _oracle_rate(p, threads, target_s):
     return p.S * p.cells * n / dt, n, dt
 
 
-def cpu_baseline(p, target_s=10.0):
+def _oracle_rate_large(threads, steps=2):
+    """The oracle on the full 4096^2 shear layer: a fixed few steps."""
+    from oracle import oracle as O
+    from paper_2006_15932_amd import workloads as W
+    p = W.shear_layer(n=4096, steps=steps, precision="fp64")
+    O.set_threads(threads)
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    t0 = time.perf_counter()
+    o.run(f, steps)
+    dt = time.perf_counter() - t0
+    return p.S * p.cells * steps / dt, dt
+
+
+def cpu_baseline(p, target_s=10.0, large=True):
     threads = max(1, min(16, os.cpu_count() or 1))
     v, n, dt = _oracle_rate(p, threads, target_s)
     v1, n1, dt1 = _oracle_rate(p, 1, target_s / 3)
-    return {"value": v, "unit": UNIT, "cores": threads, "kind": "oracle",
-            "sample": "FP64 oracle, %d Euler steps of the full %dx%d, %d-species workload "
-                      "(%.1f s, OpenMP over rows)" % (n, p.nx, p.ny, p.S, dt),
-            "single_thread_value": v1,
-            "single_thread_sample": "%d steps on 1 thread (%.1f s)" % (n1, dt1)}
+    out = {"value": v, "unit": UNIT, "cores": threads, "kind": "oracle",
+           "sample": "FP64 oracle, %d Euler steps of the full %dx%d, %d-species workload "
+                     "(%.1f s, OpenMP over rows)" % (n, p.nx, p.ny, p.S, dt),
+           "single_thread_value": v1,
+           "single_thread_sample": "%d steps on 1 thread (%.1f s)" % (n1, dt1)}
+    if large:
+        vl, dtl = _oracle_rate_large(threads)
+        out["large_grid_value"] = vl
+        out["large_grid_sample"] = ("FP64 oracle, 2 Euler steps of the 4096x4096 4-species shear "
+                                    "layer on %d threads (%.1f s)" % (threads, dtl))
+    return out
 
 
 def traffic_mode(args):
