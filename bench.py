@@ -73,7 +73,7 @@ def bytes_per_csu(precision: str, scheme: int) -> int:
     return es * (32 if scheme == 0 else 128)
 
 
-def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0):
+def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0, chain_wave=0):
     import torch
     from paper_2006_15932_amd import dbm as D
     sim = D.Simulation(p, precision=precision)
@@ -84,6 +84,8 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0):
         sim.set_option(D.DBM_OPT_TILE_ROWS, tile_rows)
     if pipeline:
         sim.set_option(D.DBM_OPT_PIPELINE, pipeline)
+    if chain_wave:
+        sim.set_option(D.DBM_OPT_CHAIN_WAVE, chain_wave)
     sim.set_fields()
     sim.step(warmup)
     sim.synchronize()
@@ -97,6 +99,7 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0, pipeline=0, rounding=0):
     kern_ms = ms / launches
     rows = sim.get_option(D.DBM_OPT_TILE_ROWS)
     sim.pipeline_in_use = sim.get_option(D.DBM_OPT_PIPELINE)
+    sim.chain_wave_in_use = sim.get_option(D.DBM_OPT_CHAIN_WAVE)
     return sim, ms, kern_ms, rows
 
 
@@ -226,7 +229,8 @@ def traffic_mode(args):
     rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs."""
     import torch
     p, _ = workload(args.workload, args.precision)
-    sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows, args.pipeline)
+    sim, _, _, rows = gpu_run(p, args.precision, 2, 2, args.tile_rows, args.pipeline,
+                              chain_wave=args.chain_wave)
     sim.time_stage_kernel(args.steps)
     sim.close()
     n = 256 << 20
@@ -248,6 +252,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--mode", default="bench", choices=["bench", "traffic"])
     ap.add_argument("--tile-rows", type=int, default=0, help="pin rows per tile (0 = autotune)")
+    ap.add_argument("--chain-wave", type=int, default=0, choices=[0, 1, 2],
+                    help="FP32 chain wavefront (S <= 3): 0 autotune, 1 off, 2 on")
     ap.add_argument("--pipeline", type=int, default=0, choices=[0, 1, 2],
                     help="FP32 row pipeline: 0 autotune, 1 off, 2 on (with --tile-rows)")
     ap.add_argument("--rounding", type=int, default=0, choices=[0, 1],
@@ -265,8 +271,9 @@ def main():
     p, desc = workload(args.workload, args.precision)
     assert p.scheme == 0, "one launch per step is assumed below"
     sim, ms, kern_ms, rows = gpu_run(p, args.precision, args.steps, args.warmup, args.tile_rows,
-                                     args.pipeline, args.rounding)
+                                     args.pipeline, args.rounding, args.chain_wave)
     pipeline = sim.pipeline_in_use
+    chain_wave = sim.chain_wave_in_use
     csu_step = p.S * p.cells
     value = csu_step * args.steps / (ms * 1e-3)
     bpl = csu_step * bytes_per_csu(args.precision, p.scheme)
@@ -288,6 +295,7 @@ def main():
                    "precision": "FP32-bulk (FP64 moments/T and conserved-row collision)"
                    if args.precision == "fp32" else "FP64", "scheme": "euler",
                    "tile_rows": rows, "row_pipeline": pipeline == 2,
+                   "chain_wavefront": chain_wave == 2,
                    "rounding": "stochastic" if args.rounding else "nearest"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

@@ -196,13 +196,20 @@ enum {
                                while row k's stencils are; 0 tuned with the
                                tile rows (default; off when the rows are set),
                                1 off, 2 on; get: 1 or 2 in use */
-  DBM_OPT_ROUNDING = 10     /* FP32-bulk stores of f: 0 round to nearest
+  DBM_OPT_ROUNDING = 10,    /* FP32-bulk stores of f: 0 round to nearest
                                (default), 1 stochastic rounding (unbiased:
                                up or down with probabilities in proportion to
                                the distances, 8 random bits per value hashed
                                from the cell, species and state, so runs are
                                deterministic); DBM_ERR_UNSUPPORTED for other
                                precisions and with the split form */
+  DBM_OPT_CHAIN_WAVE = 11   /* FP32-bulk, nspecies <= 3: one more wavefront
+                               per workgroup forms each row's mixture chain
+                               (u, T, reaction) while the species' wavefronts
+                               form their stencils; 0 tuned with the tile rows
+                               (default), 1 off, 2 on; excludes the split
+                               form and the row pipeline
+                               (DBM_ERR_UNSUPPORTED); get: 1 or 2 in use */
 };
 int dbm_set_option(dbm_handle h, int option, int value);
 int dbm_get_option(dbm_handle h, int option, int *value);

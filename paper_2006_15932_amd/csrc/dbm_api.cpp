@@ -18,10 +18,11 @@
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        const InstDev *insts,
+                        bool cw, const InstDev *insts,
                         const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
                         int out_idx, double alpha, double beta, hipStream_t st);
-hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu);
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw,
+                           int *waves_per_cu);
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
                         bool sr, hipStream_t st);
@@ -235,10 +236,13 @@ struct dbm_s {
   bool split = false;   // form in use
   bool pipe = false;    // row pipelining in use (FP32 full form)
   int pipe_opt = 0;     // DBM_OPT_PIPELINE: 0 tuned, 1 off, 2 on
+  bool cw = false;      // chain wavefront in use (FP32 full form, S <= 3)
+  int cw_opt = 0;       // DBM_OPT_CHAIN_WAVE: 0 tuned, 1 off, 2 on
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
-  int resident = 0, resident_split = 0;  // workgroups resident on the device, per form
-  int grid_cap() const { return split ? resident_split : resident; }
+  // workgroups resident on the device, per form
+  int resident = 0, resident_split = 0, resident_cw = 0;
+  int grid_cap() const { return split ? resident_split : (cw ? resident_cw : resident); }
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   long long since_check = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -285,13 +289,15 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->d_inst(),
+      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
+                          h->d_inst(),
                           h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
-        HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->d_inst(),
+        HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
+                          h->d_inst(),
                             h->d_tiles() + b, nt, grid, in_idx, fn_idx, out_idx, alpha, beta,
                             st));
       }
@@ -383,7 +389,7 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    (h->split_opt * 3 + h->pipe_opt) * 2 + h->sr};
+                    ((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -405,11 +411,17 @@ int ensure_tuned(dbm_handle h) {
     for (int f = 0; f < 2; ++f) {
       if (!tune_form && f != form) continue;
       h->split = f == 1;
-      // the row pipeline exists for the FP32 full form
+      // the row pipeline (pp 1) and the chain wavefront (pp 2) exist for the
+      // FP32 full form, the latter for S <= 3
       const bool can_pipe = h->fp32 && f == 0;
-      for (int pp = 0; pp < (can_pipe ? 2 : 1); ++pp) {
-        if ((h->pipe_opt == 1 && pp == 1) || (h->pipe_opt == 2 && can_pipe && pp == 0)) continue;
+      const bool can_cw = can_pipe && h->S <= 3 && h->resident_cw > 0;
+      for (int pp = 0; pp < 3; ++pp) {
+        if (pp == 1 && (!can_pipe || h->pipe_opt == 1)) continue;
+        if (pp == 2 && (!can_cw || h->cw_opt == 1)) continue;
+        if (h->pipe_opt == 2 && can_pipe && pp != 1) continue;
+        if (h->cw_opt == 2 && can_cw && pp != 2) continue;
         h->pipe = pp == 1;
+        h->cw = pp == 2;
         for (int r : cands) {
           if (r > 2 * maxny && r > 1) break;
           build_tiles(h, r);
@@ -427,7 +439,7 @@ int ensure_tuned(dbm_handle h) {
           if (ms < best) {
             best = ms;
             best_rows = r;
-            best_form = f + 2 * pp;
+            best_form = f | (pp == 1 ? 2 : 0) | (pp == 2 ? 4 : 0);
           }
         }
       }
@@ -440,11 +452,13 @@ int ensure_tuned(dbm_handle h) {
   if (h->tile_rows_opt > 0) {  // fixed rows: the form and pipeline the options ask for
     form = h->split_opt == 2 ? 1 : 0;
     if (form == 0 && h->fp32 && h->pipe_opt == 2) form = 2;
+    if (form == 0 && h->fp32 && h->cw_opt == 2 && h->S <= 3 && h->resident_cw > 0) form = 4;
   }
-  if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) == 1) ||
-      h->pipe != (form >= 2)) {
-    h->split = (form & 1) == 1;
-    h->pipe = form >= 2;
+  if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) != 0) ||
+      h->pipe != ((form & 2) != 0) || h->cw != ((form & 4) != 0)) {
+    h->split = (form & 1) != 0;
+    h->pipe = (form & 2) != 0;
+    h->cw = (form & 4) != 0;
     build_tiles(h, want);
     int rc = upload_tiles(h);
     if (rc) return rc;
@@ -654,17 +668,20 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
   if ((rc = run_probe(h))) return bail(rc);
   if (g_probe_state < 0) h->fused_ok = false;
   if (h->fused_ok) {
-    int per_cu = 0, per_cu_split = 0, dev = 0;
+    int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, dev = 0;
     hipDeviceProp_t prop;
     const bool rk3 = h->scheme == DBM_TVD_RK3;
-    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, &per_cu)) != hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, &per_cu_split)) != hipSuccess ||
+    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, &per_cu)) != hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, false, &per_cu_split)) !=
+            hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, &per_cu_cw)) != hipSuccess ||
         (e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
       return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
     auto round_xcd = [](int r) { return std::max(kNumXcd, (r / kNumXcd) * kNumXcd); };
     h->resident = round_xcd(per_cu * prop.multiProcessorCount);
     h->resident_split = round_xcd(per_cu_split * prop.multiProcessorCount);
+    h->resident_cw = per_cu_cw > 0 ? round_xcd(per_cu_cw * prop.multiProcessorCount) : 0;
   }
   *out = h;
   return DBM_OK;
@@ -863,13 +880,28 @@ int dbm_set_option(dbm_handle h, int option, int value) {
         return fail(DBM_ERR_UNSUPPORTED, "the split form has no FP32X storage variant");
       if (value == 2 && h->sr)
         return fail(DBM_ERR_UNSUPPORTED, "the split form has no stochastic rounding");
+      if (value == 2 && h->cw_opt == 2)
+        return fail(DBM_ERR_UNSUPPORTED, "the chain wavefront excludes the split form");
       h->split_opt = value;
       h->rows = 0;
       h->tiles.clear();
       break;
     case DBM_OPT_PIPELINE:
       if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "pipeline must be 0, 1 or 2");
+      if (value == 2 && h->cw_opt == 2)
+        return fail(DBM_ERR_UNSUPPORTED, "the chain wavefront replaces the row pipeline");
       h->pipe_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
+    case DBM_OPT_CHAIN_WAVE:
+      if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "chain wave must be 0, 1 or 2");
+      if (value == 2 && (h->prec != DBM_FP32_BULK || h->S > 3 || h->resident_cw == 0))
+        return fail(DBM_ERR_UNSUPPORTED, "the chain wavefront needs FP32-bulk and S <= 3");
+      if (value == 2 && (h->split_opt == 2 || h->pipe_opt == 2))
+        return fail(DBM_ERR_UNSUPPORTED,
+                    "the chain wavefront excludes the split form and the row pipeline");
+      h->cw_opt = value;
       h->rows = 0;
       h->tiles.clear();
       break;
@@ -902,6 +934,7 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
     case DBM_OPT_PIPELINE: *value = h->pipe ? 2 : 1; break;
     case DBM_OPT_ROUNDING: *value = h->sr; break;
+    case DBM_OPT_CHAIN_WAVE: *value = h->cw ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;

@@ -764,6 +764,16 @@ static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) ==
 constexpr int kXPlanes = 12;
 constexpr int kHaloLanes = 3 * kXPlanes;
 
+// Chain wavefront (CW, FP32, S <= 3): the workgroup has one more wavefront,
+// which forms the mixture chain (u, T, reaction extents, T*) of row k+1
+// from the species' moments while the species wavefronts form row k's
+// collision and stencils, and publishes it through LDS (u_x, u_y, T*, dn^s
+// per cell).  One barrier per row, as without it: the species publish row
+// k+1's moments (from the prefetched values) and find row k's chain formed
+// during row k-1.  The species wavefronts shed the FP64 chain and with
+// S = 3 the fourth SIMD of a CU gets work.
+template <int S, bool CW> constexpr int kChainRows = CW ? 3 + S : 1;
+
 // Software pipeline over rows (PIPE, FP32): row k+1's moments, mixture
 // chain and collision are formed while row k's stencils are (their inputs
 // are already in registers: the prefetched row and the carried y-state),
@@ -783,11 +793,12 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 // One wavefront's share of a tile: species `s`, 64 lanes = columns
 // x0 .. x0+63, rows y0 .. y0+rows-1.  `mom` is the workgroup's LDS
 // exchange of per-cell FP64 moments, double-buffered by row parity.
-template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR>
+template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR, bool CW>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
                                            typename Stor<ST>::C alpha,
-                                           double (*mom)[4 * S][kWave]) {
+                                           double (*mom)[4 * S][kWave],
+                                           double (*chn)[kChainRows<S, CW>][kWave]) {
   typedef typename Stor<ST>::C T;                  // arithmetic type
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
@@ -895,16 +906,35 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn_own, cs.ux, cs.uy,
                        cs.Tst, dfo);
   };
+  // Chain wavefront: this species' FP64 moments of row k (values fr) to LDS.
+  auto publish = [&](int k, const T *fr, SpC &me) {
+    T oA[4], oB[4], oX[4], oY[4];
+    orbit_parts<T>(fr, oA, oB, oX, oY);
+    double n0, jx0, jy0, E0;
+    species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
+    double(*mb)[kWave] = mom[k & 1];
+    mb[0 * S + s][lane] = n0;
+    mb[1 * S + s][lane] = jx0;
+    mb[2 * S + s][lane] = jy0;
+    mb[3 * S + s][lane] = E0;
+  };
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
   // values of row k+D-1, so D rows of loads are in flight.  (Issuing the
   // first slots before the first collision measured slower than after it.)
   T ring[kPrefetch][kNV];
   T hring[kPrefetch];
   constexpr bool kPipe = PIPE && sizeof(T) == 4;
+  constexpr bool kCW = CW && std::is_same<ST, float>::value;
+  static_assert(!(kPipe && kCW), "the chain wavefront replaces the row pipeline");
   T df[kNV];
   if constexpr (kPipe) {   // needs row y0 only: overlaps the other rows' loads
     SpC *sp = launder(as_const(I.sp));
     collide(y0, c, sp, sp[s], df);
+  }
+  if constexpr (kCW) {     // row y0's moments for the chain wavefront's first chain
+    SpC *sp = launder(as_const(I.sp));
+    publish(y0, c, sp[s]);
+    __syncthreads();
   }
   start_state();
 #pragma unroll
@@ -953,8 +983,27 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
         cgy[g] = Tab<T>::cgy(me, g);
       }
     }
-    // Row k's collision: from the previous row (pipelined) or here.
-    if constexpr (!kPipe) collide(k, c, sp, me, df);
+    // Row k's collision: from the previous row (pipelined) or here.  With a
+    // chain wavefront: publish row k+1's moments, one barrier, then row k's
+    // collision from the chain the chain wavefront formed during row k-1.
+    if constexpr (!kPipe && !kCW) collide(k, c, sp, me, df);
+    if constexpr (kCW) {
+      if (k + 1 < yend) {
+        T fn1[kNV];
+#pragma unroll
+        for (int i = 0; i < kNV; ++i) fn1[i] = plane_sy(i) < 0 ? y1[i] : cur[i];
+        publish(k + 1, fn1, me);
+      }
+      __syncthreads();
+      double(*cb)[kWave] = chn[k & 1];
+      const double ux = cb[0][lane], uy = cb[1][lane], Tst = cb[2][lane];
+      const double dn = cb[3 + s][lane];
+      T oA[4], oB[4], oX[4], oY[4];
+      double n0, jx0, jy0, E0;
+      orbit_parts<T>(c, oA, oB, oX, oY);
+      species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
+      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, df);
+    }
     // Pipelined: row k+1's values are the prefetched row (v_y >= 0) or the
     // carried next value (v_y < 0); form its collision now.
     T dfn[kNV];
@@ -1336,21 +1385,49 @@ template <> struct Occ<float> { static constexpr int kMinWaves = DBM_MIN_WAVES_F
 template <> struct Occ<double> { static constexpr int kMinWaves = DBM_MIN_WAVES_F64; };
 template <> struct Occ<f32x> { static constexpr int kMinWaves = DBM_MIN_WAVES_F64; };
 
-// One workgroup = S wavefronts, wavefront w advancing species w of a tile;
-// tiles are taken persistently from the table in XCD-grouped order.
-template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR>
-__global__ __launch_bounds__(kWave * S, Occ<ST>::kMinWaves) void k_fused_stage(const InstDev *__restrict__ insts,
-                                                           const Tile *__restrict__ tiles,
-                                                           int ntiles, int in_idx, int fn_idx,
-                                                           int out_idx,
-                                                           typename Stor<ST>::C alpha,
-                                                           int remap) {
+// The chain wavefront's part of a tile: after the species wavefronts have
+// published row y0's moments (first barrier), the chain of row k is formed
+// before row k's barrier, from moments published before row k-1's barrier.
+// One barrier per row plus the first, as in fused_tile with CW.
+template <typename T, int S>
+__device__ __forceinline__ void chain_tile(const InstDev &I, int y0, int rows,
+                                           double (*mom)[4 * S][kWave],
+                                           double (*chn)[kChainRows<S, true>][kWave]) {
+  const int lane = threadIdx.x & (kWave - 1);
+  __syncthreads();   // row y0's moments published
+  for (int k = y0; k < y0 + rows; ++k) {
+    SpC *sp = launder(as_const(I.sp));
+    double(*mb)[kWave] = mom[k & 1];
+    CellState cs;
+    cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
+    double(*cb)[kWave] = chn[k & 1];
+    cb[0][lane] = cs.ux;
+    cb[1][lane] = cs.uy;
+    cb[2][lane] = cs.Tst;
+#pragma unroll
+    for (int q = 0; q < S; ++q) cb[3 + q][lane] = cs.dn[q];
+    __syncthreads();   // row k's barrier
+  }
+}
+
+// One workgroup = S wavefronts, wavefront w advancing species w of a tile
+// (plus the chain wavefront, index S, with CW); tiles are taken
+// persistently from the table in XCD-grouped order.
+template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR, bool CW>
+__global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), Occ<ST>::kMinWaves) void k_fused_stage(
+    const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
+    int fn_idx, int out_idx, typename Stor<ST>::C alpha, int remap) {
   __shared__ double mom[2][4 * S][kWave];
+  __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
-    fused_tile<ST, S, LIM, RKC, PIPE, SR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
-                                          out_idx, alpha, mom);
+    if (CW && s == S) {
+      if constexpr (CW) chain_tile<typename Stor<ST>::C, S>(insts[t.inst], t.y0, t.rows, mom, chn);
+    } else {
+      fused_tile<ST, S, LIM, RKC, PIPE, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx,
+                                                fn_idx, out_idx, alpha, mom, chn);
+    }
     __syncthreads();
   }
 }
@@ -1935,7 +2012,7 @@ struct FusedLaunch {
   const Tile *tiles;
   int ntiles, grid, in_idx, fn_idx, out_idx, remap;
   double alpha, beta;
-  bool split, pipe, sr;  // split form, row pipeline, stochastic rounding
+  bool split, pipe, sr, cw;  // split form, row pipeline, stochastic rounding, chain wavefront
   hipStream_t st;
 };
 
@@ -1950,18 +2027,25 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
       return hipGetLastError();
     }
   }
-#define DBM_FUSED_LAUNCH(P, R)                                                                  \
-  hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R>), dim3(a.grid), dim3(kWave * S), 0,    \
-                     a.st, a.insts, a.tiles, a.ntiles, a.in_idx, a.fn_idx, a.out_idx,           \
-                     (T)a.alpha, a.remap)
+#define DBM_FUSED_LAUNCH(P, R, C)                                                              \
+  hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R, C>), dim3(a.grid),                   \
+                     dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
+                     a.in_idx, a.fn_idx, a.out_idx, (T)a.alpha, a.remap)
+  if constexpr (std::is_same<ST, float>::value && S <= 3) {
+    if (a.cw) {
+      if (a.sr) DBM_FUSED_LAUNCH(false, true, true); else DBM_FUSED_LAUNCH(false, false, true);
+      return hipGetLastError();
+    }
+  }
+  if (a.cw) return hipErrorInvalidValue;
   if constexpr (std::is_same<ST, float>::value) {
     if (a.pipe) {
-      if (a.sr) DBM_FUSED_LAUNCH(true, true); else DBM_FUSED_LAUNCH(true, false);
+      if (a.sr) DBM_FUSED_LAUNCH(true, true, false); else DBM_FUSED_LAUNCH(true, false, false);
     } else {
-      if (a.sr) DBM_FUSED_LAUNCH(false, true); else DBM_FUSED_LAUNCH(false, false);
+      if (a.sr) DBM_FUSED_LAUNCH(false, true, false); else DBM_FUSED_LAUNCH(false, false, false);
     }
   } else {
-    DBM_FUSED_LAUNCH(false, false);
+    DBM_FUSED_LAUNCH(false, false, false);
   }
 #undef DBM_FUSED_LAUNCH
   return hipGetLastError();
@@ -1991,14 +2075,16 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 
 // prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
 // sr: stochastic rounding of the stores (FP32-bulk full form only).
+// cw: chain wavefront (FP32-bulk full form, S <= 3, no row pipeline).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        const InstDev *insts, const Tile *tiles, int ntiles, int grid,
+                        bool cw, const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                         hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   if (sr && (prec != DBM_FP32_BULK || split)) return hipErrorInvalidValue;
+  if (cw && (prec != DBM_FP32_BULK || split || pipe || S > 3)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
-                      alpha, beta, split, pipe, sr, st};
+                      alpha, beta, split, pipe, sr, cw, st};
   switch (prec) {
     case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
     case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);
@@ -2007,11 +2093,31 @@ hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pip
 }
 
 template <typename ST, int S, int LIM, bool RKC>
-constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false, false>;
+constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false, false, false>;
+template <typename ST, int S, int LIM, bool RKC>
+constexpr auto k_fused_stage_cw = k_fused_stage<ST, S, LIM, RKC, false, false, true>;
 
-hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *waves_per_cu) {
+#define DBM_PICK1_CW(SS)                                                                        \
+  fn = lim == DBM_LIM_MINMOD                                                                   \
+           ? (rkc ? (const void *)k_fused_stage_cw<float, SS, DBM_LIM_MINMOD, true>            \
+                  : (const void *)k_fused_stage_cw<float, SS, DBM_LIM_MINMOD, false>)          \
+           : (rkc ? (const void *)k_fused_stage_cw<float, SS, DBM_LIM_NONE, true>              \
+                  : (const void *)k_fused_stage_cw<float, SS, DBM_LIM_NONE, false>)
+// Workgroups of the stage kernel resident per CU (waves_per_cu), for the
+// full form, the split form (split) or the chain-wavefront form (cw).
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw,
+                           int *waves_per_cu) {
   const void *fn = nullptr;
   if (prec == DBM_FP32X) split = false;  // full form only
+  if (cw) {
+    if (prec != DBM_FP32_BULK || S > 3) {
+      *waves_per_cu = 0;
+      return hipSuccess;
+    }
+    switch (S) { case 1: DBM_PICK1_CW(1); break; case 2: DBM_PICK1_CW(2); break;
+                 default: DBM_PICK1_CW(3); break; }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * (S + 1), 0);
+  }
 #define DBM_PICK1(K, T, SS)                                                                     \
   fn = lim == DBM_LIM_MINMOD                                                                   \
            ? (rkc ? (const void *)K<T, SS, DBM_LIM_MINMOD, true>                               \
@@ -2037,6 +2143,7 @@ hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, int *
 #undef DBM_PICK
 #undef DBM_PICKX
 #undef DBM_PICK1
+#undef DBM_PICK1_CW
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S * (split ? 2 : 1),
                                                       0);
 }

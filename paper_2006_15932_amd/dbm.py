@@ -28,6 +28,7 @@ DBM_OPT_PATH, DBM_OPT_GRAPH, DBM_OPT_TILE_ROWS, DBM_OPT_CHECK_EVERY = 1, 2, 3, 4
 DBM_OPT_BATCH_MODE, DBM_OPT_GRAPH_CHUNK, DBM_OPT_PERSISTENT, DBM_OPT_SPLIT = 5, 6, 7, 8
 DBM_OPT_PIPELINE = 9
 DBM_OPT_ROUNDING = 10
+DBM_OPT_CHAIN_WAVE = 11
 
 NV = 16
 
