@@ -203,7 +203,7 @@ enum {
                                from the cell, species and state, so runs are
                                deterministic); DBM_ERR_UNSUPPORTED for other
                                precisions and with the split form */
-  DBM_OPT_CHAIN_WAVE = 11   /* FP32-bulk, nspecies <= 3: one more wavefront
+  DBM_OPT_CHAIN_WAVE = 11   /* one-pass path, nspecies <= 3: one more wavefront
                                per workgroup forms each row's mixture chain
                                (u, T, reaction) while the species' wavefronts
                                form their stencils; 0 tuned with the tile rows

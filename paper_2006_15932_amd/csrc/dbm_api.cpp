@@ -236,7 +236,7 @@ struct dbm_s {
   bool split = false;   // form in use
   bool pipe = false;    // row pipelining in use (FP32 full form)
   int pipe_opt = 0;     // DBM_OPT_PIPELINE: 0 tuned, 1 off, 2 on
-  bool cw = false;      // chain wavefront in use (FP32 full form, S <= 3)
+  bool cw = false;      // chain wavefront in use (full form, S <= 3)
   int cw_opt = 0;       // DBM_OPT_CHAIN_WAVE: 0 tuned, 1 off, 2 on
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
@@ -411,10 +411,10 @@ int ensure_tuned(dbm_handle h) {
     for (int f = 0; f < 2; ++f) {
       if (!tune_form && f != form) continue;
       h->split = f == 1;
-      // the row pipeline (pp 1) and the chain wavefront (pp 2) exist for the
-      // FP32 full form, the latter for S <= 3
+      // the row pipeline (pp 1) exists for the FP32 full form, the chain
+      // wavefront (pp 2) for the full form with S <= 3
       const bool can_pipe = h->fp32 && f == 0;
-      const bool can_cw = can_pipe && h->S <= 3 && h->resident_cw > 0;
+      const bool can_cw = f == 0 && h->S <= 3 && h->resident_cw > 0;
       for (int pp = 0; pp < 3; ++pp) {
         if (pp == 1 && (!can_pipe || h->pipe_opt == 1)) continue;
         if (pp == 2 && (!can_cw || h->cw_opt == 1)) continue;
@@ -452,7 +452,7 @@ int ensure_tuned(dbm_handle h) {
   if (h->tile_rows_opt > 0) {  // fixed rows: the form and pipeline the options ask for
     form = h->split_opt == 2 ? 1 : 0;
     if (form == 0 && h->fp32 && h->pipe_opt == 2) form = 2;
-    if (form == 0 && h->fp32 && h->cw_opt == 2 && h->S <= 3 && h->resident_cw > 0) form = 4;
+    if (form == 0 && h->cw_opt == 2 && h->S <= 3 && h->resident_cw > 0) form = 4;
   }
   if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) != 0) ||
       h->pipe != ((form & 2) != 0) || h->cw != ((form & 4) != 0)) {
@@ -896,8 +896,8 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       break;
     case DBM_OPT_CHAIN_WAVE:
       if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "chain wave must be 0, 1 or 2");
-      if (value == 2 && (h->prec != DBM_FP32_BULK || h->S > 3 || h->resident_cw == 0))
-        return fail(DBM_ERR_UNSUPPORTED, "the chain wavefront needs FP32-bulk and S <= 3");
+      if (value == 2 && (h->S > 3 || h->resident_cw == 0 || !h->fused_ok))
+        return fail(DBM_ERR_UNSUPPORTED, "the chain wavefront needs the one-pass path and S <= 3");
       if (value == 2 && (h->split_opt == 2 || h->pipe_opt == 2))
         return fail(DBM_ERR_UNSUPPORTED,
                     "the chain wavefront excludes the split form and the row pipeline");

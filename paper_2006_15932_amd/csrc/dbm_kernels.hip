@@ -764,7 +764,7 @@ static_assert(xplane(0) == 0 && xplane(1) == 2 && xplane(5) == 7 && xplane(7) ==
 constexpr int kXPlanes = 12;
 constexpr int kHaloLanes = 3 * kXPlanes;
 
-// Chain wavefront (CW, FP32, S <= 3): the workgroup has one more wavefront,
+// Chain wavefront (CW, S <= 3): the workgroup has one more wavefront,
 // which forms the mixture chain (u, T, reaction extents, T*) of row k+1
 // from the species' moments while the species wavefronts form row k's
 // collision and stencils, and publishes it through LDS (u_x, u_y, T*, dn^s
@@ -773,6 +773,14 @@ constexpr int kHaloLanes = 3 * kXPlanes;
 // during row k-1.  The species wavefronts shed the FP64 chain and with
 // S = 3 the fourth SIMD of a CU gets work.
 template <int S, bool CW> constexpr int kChainRows = CW ? 3 + S : 1;
+
+// Rows a tile's row loop runs: FP64 arithmetic runs whole ring cycles,
+// computing (not storing) up to kPrefetch-1 rows past the tile (kSteady in
+// fused_tile); the chain wavefront runs the same number of row barriers.
+template <typename T> constexpr bool kSteadyRows = sizeof(T) == 8;
+__device__ __forceinline__ int rows_run(bool steady, int rows) {
+  return steady ? (rows + kPrefetch - 1) / kPrefetch * kPrefetch : rows;
+}
 
 // Software pipeline over rows (PIPE, FP32): row k+1's moments, mixture
 // chain and collision are formed while row k's stencils are (their inputs
@@ -924,7 +932,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   T ring[kPrefetch][kNV];
   T hring[kPrefetch];
   constexpr bool kPipe = PIPE && sizeof(T) == 4;
-  constexpr bool kCW = CW && std::is_same<ST, float>::value;
+  constexpr bool kCW = CW;
   static_assert(!(kPipe && kCW), "the chain wavefront replaces the row pipeline");
   T df[kNV];
   if constexpr (kPipe) {   // needs row y0 only: overlaps the other rows' loads
@@ -947,7 +955,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   // tile's end are then computed (from in-range rows: map_y wraps, clamps
   // or mirrors every index) but not stored.  In FP32 the conditional form
   // measured faster.
-  constexpr bool kSteady = sizeof(T) == 8;
+  constexpr bool kSteady = kSteadyRows<T>;
   auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
     if (kSteady || k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
     const int rk = k * nx;
@@ -1395,7 +1403,8 @@ __device__ __forceinline__ void chain_tile(const InstDev &I, int y0, int rows,
                                            double (*chn)[kChainRows<S, true>][kWave]) {
   const int lane = threadIdx.x & (kWave - 1);
   __syncthreads();   // row y0's moments published
-  for (int k = y0; k < y0 + rows; ++k) {
+  const int nrun = rows_run(kSteadyRows<T>, rows);
+  for (int k = y0; k < y0 + nrun; ++k) {
     SpC *sp = launder(as_const(I.sp));
     double(*mb)[kWave] = mom[k & 1];
     CellState cs;
@@ -2031,7 +2040,7 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
   hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R, C>), dim3(a.grid),                   \
                      dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
                      a.in_idx, a.fn_idx, a.out_idx, (T)a.alpha, a.remap)
-  if constexpr (std::is_same<ST, float>::value && S <= 3) {
+  if constexpr (S <= 3) {
     if (a.cw) {
       if (a.sr) DBM_FUSED_LAUNCH(false, true, true); else DBM_FUSED_LAUNCH(false, false, true);
       return hipGetLastError();
@@ -2075,14 +2084,14 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 
 // prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
 // sr: stochastic rounding of the stores (FP32-bulk full form only).
-// cw: chain wavefront (FP32-bulk full form, S <= 3, no row pipeline).
+// cw: chain wavefront (full form, S <= 3, no row pipeline).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
                         bool cw, const InstDev *insts, const Tile *tiles, int ntiles, int grid,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta,
                         hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   if (sr && (prec != DBM_FP32_BULK || split)) return hipErrorInvalidValue;
-  if (cw && (prec != DBM_FP32_BULK || split || pipe || S > 3)) return hipErrorInvalidValue;
+  if (cw && (split || pipe || S > 3)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
                       alpha, beta, split, pipe, sr, cw, st};
   switch (prec) {
@@ -2097,12 +2106,15 @@ constexpr auto k_fused_stage_np = k_fused_stage<ST, S, LIM, RKC, false, false, f
 template <typename ST, int S, int LIM, bool RKC>
 constexpr auto k_fused_stage_cw = k_fused_stage<ST, S, LIM, RKC, false, false, true>;
 
-#define DBM_PICK1_CW(SS)                                                                        \
+#define DBM_PICK1_CW(T, SS)                                                                     \
   fn = lim == DBM_LIM_MINMOD                                                                   \
-           ? (rkc ? (const void *)k_fused_stage_cw<float, SS, DBM_LIM_MINMOD, true>            \
-                  : (const void *)k_fused_stage_cw<float, SS, DBM_LIM_MINMOD, false>)          \
-           : (rkc ? (const void *)k_fused_stage_cw<float, SS, DBM_LIM_NONE, true>              \
-                  : (const void *)k_fused_stage_cw<float, SS, DBM_LIM_NONE, false>)
+           ? (rkc ? (const void *)k_fused_stage_cw<T, SS, DBM_LIM_MINMOD, true>                \
+                  : (const void *)k_fused_stage_cw<T, SS, DBM_LIM_MINMOD, false>)              \
+           : (rkc ? (const void *)k_fused_stage_cw<T, SS, DBM_LIM_NONE, true>                  \
+                  : (const void *)k_fused_stage_cw<T, SS, DBM_LIM_NONE, false>)
+#define DBM_PICK_CW(T)                                                                          \
+  switch (S) { case 1: DBM_PICK1_CW(T, 1); break; case 2: DBM_PICK1_CW(T, 2); break;          \
+               default: DBM_PICK1_CW(T, 3); break; }
 // Workgroups of the stage kernel resident per CU (waves_per_cu), for the
 // full form, the split form (split) or the chain-wavefront form (cw).
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw,
@@ -2110,12 +2122,13 @@ hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool 
   const void *fn = nullptr;
   if (prec == DBM_FP32X) split = false;  // full form only
   if (cw) {
-    if (prec != DBM_FP32_BULK || S > 3) {
+    if (S > 3) {
       *waves_per_cu = 0;
       return hipSuccess;
     }
-    switch (S) { case 1: DBM_PICK1_CW(1); break; case 2: DBM_PICK1_CW(2); break;
-                 default: DBM_PICK1_CW(3); break; }
+    if (prec == DBM_FP32_BULK) { DBM_PICK_CW(float); }
+    else if (prec == DBM_FP32X) { DBM_PICK_CW(f32x); }
+    else { DBM_PICK_CW(double); }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * (S + 1), 0);
   }
 #define DBM_PICK1(K, T, SS)                                                                     \
@@ -2144,6 +2157,7 @@ hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool 
 #undef DBM_PICKX
 #undef DBM_PICK1
 #undef DBM_PICK1_CW
+#undef DBM_PICK_CW
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn, kWave * S * (split ? 2 : 1),
                                                       0);
 }
