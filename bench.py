@@ -314,6 +314,15 @@ def main():
         sx, msx, _, _ = gpu_run(px, "fp32x", max(1, args.steps // 5), 20)
         extra["fp32x_value"] = csu_step * max(1, args.steps // 5) / (msx * 1e-3)
         sx.close()
+        # the same workload with the TVD-RK3 time scheme (three stage launches per step)
+        pr3 = p.with_(scheme=1)
+        n3 = max(1, args.steps // 5)
+        sr3, ms3, k3, _ = gpu_run(pr3, args.precision, n3, 10)
+        extra["rk3"] = {"value": csu_step * n3 / (ms3 * 1e-3), "ms_per_step": ms3 / n3,
+                        "ms_per_stage_launch": k3,
+                        "algorithmic_gbs": csu_step * bytes_per_csu(args.precision, 1)
+                        / 3 / (k3 * 1e-3) / 1e9}
+        sr3.close()
         extra["plain_fp64_value"] = plain_fp64(p)
         extra["speedup_fp32_fused_vs_plain_fp64"] = value / extra["plain_fp64_value"]
         extra["batched"] = batched()
