@@ -304,6 +304,10 @@ def main():
                      "achievable_copy_gbs": copy_gbs,
                      "frac_of_achievable": achieved / copy_gbs},
     }
+    if traffic:
+        # measured HBM bytes (rocprofv3 counters, calibrated) over the launch time
+        line["roofline"]["traffic_gbs"] = traffic / (kern_ms * 1e-3) / 1e9
+        line["roofline"]["traffic_frac"] = line["roofline"]["traffic_gbs"] / HBM_PEAK_GBS
     if not args.no_extra:
         extra = {}
         p64, _ = workload(args.workload, "fp64")
