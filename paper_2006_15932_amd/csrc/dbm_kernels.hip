@@ -1006,10 +1006,13 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       double(*cb)[kWave] = chn[k & 1];
       const double ux = cb[0][lane], uy = cb[1][lane], Tst = cb[2][lane];
       const double dn = cb[3 + s][lane];
+      // Row k's own moments are the ones this wavefront published for the
+      // chain (from the same values); only this wavefront writes its slots.
+      double(*mk)[kWave] = mom[k & 1];
+      const double n0 = mk[0 * S + s][lane], jx0 = mk[1 * S + s][lane];
+      const double jy0 = mk[2 * S + s][lane], E0 = mk[3 * S + s][lane];
       T oA[4], oB[4], oX[4], oY[4];
-      double n0, jx0, jy0, E0;
       orbit_parts<T>(c, oA, oB, oX, oY);
-      species_moments<T>(me, oA, oX, oY, n0, jx0, jy0, E0);
       collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, df);
     }
     // Pipelined: row k+1's values are the prefetched row (v_y >= 0) or the
