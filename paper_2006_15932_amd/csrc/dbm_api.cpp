@@ -160,6 +160,10 @@ size_t esize(const dbm_config &c) {
   return c.precision == DBM_FP32_BULK ? 4 : (c.precision == DBM_FP32X ? 6 : 8);
 }
 size_t csize(const dbm_config &c) { return c.precision == DBM_FP32_BULK ? 4 : 8; }
+// plane stride of the f buffers, in elements
+size_t pstride(const dbm_config &c) {
+  return plane_stride((size_t)c.nx * c.ny, c.precision == DBM_FP64 ? 8 : 4);
+}
 
 void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   const int S = cfgs[0].nspecies;
@@ -187,7 +191,7 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   L.scratch_off.resize(ninst);
   for (int k = 0; k < ninst; ++k) {
     const size_t cells = (size_t)cfgs[k].nx * cfgs[k].ny;
-    const size_t fbytes = (size_t)S * kNV * cells * esize(cfgs[k]);
+    const size_t fbytes = (size_t)S * kNV * pstride(cfgs[k]) * esize(cfgs[k]);
     for (int b = 0; b < 3; ++b) {
       L.buf_off[b][k] = off;
       off = align_up(off + fbytes);
@@ -250,6 +254,7 @@ struct dbm_s {
   const InstDev *d_inst() const { return (const InstDev *)(ws + L.inst_off); }
   const Tile *d_tiles() const { return (const Tile *)(ws + L.tile_off); }
   size_t cells(int k) const { return (size_t)cfg[k].nx * cfg[k].ny; }
+  size_t ps(int k) const { return pstride(cfg[k]); }
 };
 
 namespace {
@@ -402,7 +407,7 @@ int ensure_tuned(dbm_handle h) {
     if (h->scheme == DBM_TVD_RK3) {  // give the timed stage realistic inputs
       for (int k = 0; k < h->ninst; ++k)
         HIPCHK(hipMemcpyAsync(h->inst[k].buf[1], h->inst[k].buf[0],
-                              (size_t)h->S * kNV * h->cells(k) * esize(h->cfg[k]),
+                              (size_t)h->S * kNV * h->ps(k) * esize(h->cfg[k]),
                               hipMemcpyDeviceToDevice, h->stream));
     }
     const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
@@ -599,12 +604,13 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     h->cfg[k].chem = h->chem[k].empty() ? nullptr : h->chem[k].data();
     if (cfgs[k].bc_x == DBM_BC_WALL) h->fused_ok = false;
     // the one-pass kernel addresses one species' 16 planes with 32-bit offsets
-    if ((double)kNV * cfgs[k].nx * (double)cfgs[k].ny * (h->prec == DBM_FP64 ? 8.0 : 4.0) >=
+    if ((double)kNV * (double)pstride(cfgs[k]) * (h->prec == DBM_FP64 ? 8.0 : 4.0) >=
         4294967296.0)
       h->fused_ok = false;
     InstDev d;
     std::memset(&d, 0, sizeof(d));
     for (int b = 0; b < 3; ++b) d.buf[b] = h->ws + L.buf_off[b][k];
+    d.ps = pstride(cfgs[k]);
     d.scratch = h->ws + L.scratch_off[k];
     d.sp = (const SpeciesDev *)(h->ws + L.sp_off) + (size_t)k * h->S;
     d.nx = cfgs[k].nx;
@@ -718,15 +724,16 @@ int dbm_set_f(dbm_handle h, int inst, const double *f) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!f) return fail(DBM_ERR_ARG, "NULL f");
-  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
+  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV, ps = h->ps(inst);
   void *dst = h->inst[inst].buf[h->cur];
   if (h->prec == DBM_FP64) {
-    HIPCHK(hipMemcpyAsync(dst, f, sizeof(double) * nplanes * cells, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(dst, sizeof(double) * ps, f, sizeof(double) * cells,
+                            sizeof(double) * cells, nplanes, hipMemcpyHostToDevice, h->stream));
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
       HIPCHK(hipMemcpyAsync(stage, f + p * cells, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
-      HIPCHK(launch_narrow(h->prec, stage, dst, nplanes * cells, p * cells, cells, h->stream));
+      HIPCHK(launch_narrow(h->prec, stage, dst, nplanes * ps, p * ps, cells, h->stream));
     }
   }
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -737,14 +744,15 @@ int dbm_get_f(dbm_handle h, int inst, double *f) {
   int rc = check_inst(h, inst);
   if (rc) return rc;
   if (!f) return fail(DBM_ERR_ARG, "NULL f");
-  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV;
+  const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV, ps = h->ps(inst);
   const void *src = h->inst[inst].buf[h->cur];
   if (h->prec == DBM_FP64) {
-    HIPCHK(hipMemcpyAsync(f, src, sizeof(double) * nplanes * cells, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpy2DAsync(f, sizeof(double) * cells, src, sizeof(double) * ps,
+                            sizeof(double) * cells, nplanes, hipMemcpyDeviceToHost, h->stream));
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
-      HIPCHK(launch_widen(h->prec, src, nplanes * cells, p * cells, stage, cells, h->stream));
+      HIPCHK(launch_widen(h->prec, src, nplanes * ps, p * ps, stage, cells, h->stream));
       HIPCHK(hipMemcpyAsync(f + p * cells, stage, sizeof(double) * cells, hipMemcpyDeviceToHost, h->stream));
     }
   }

@@ -281,8 +281,9 @@ template <typename ST> struct FV {
     }
   }
 };
+// Values of one f buffer (each part, for FP32X): S x 16 planes of I.ps.
 __device__ __forceinline__ size_t nvals(const InstDev &I) {
-  return (size_t)I.S * kNV * (size_t)I.nx * (size_t)I.ny;
+  return (size_t)I.S * kNV * I.ps;
 }
 template <typename ST> __device__ __forceinline__ FV<ST> fview(const InstDev &I, int b) {
   return FV<ST>(I.buf[b], nvals(I));
@@ -297,7 +298,7 @@ template <typename ST> struct FBuf {
   rsrc_t hi, lo;
   uint32_t plb_hi, plb_lo;  // bytes per plane of each part
   __device__ FBuf(const InstDev &I, int b, int s) {
-    const size_t plane = (size_t)I.nx * I.ny;
+    const size_t plane = I.ps;
     plb_hi = (uint32_t)plane * es;
     plb_lo = (uint32_t)plane * 2u;
     const size_t first = (size_t)s * kNV * plane;
@@ -1165,7 +1166,7 @@ __device__ __forceinline__ void fused_tile_split(const InstDev &I, const int s, 
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
   constexpr uint32_t es = sizeof(T);
-  const size_t plane = (size_t)nx * (size_t)ny;
+  const size_t plane = I.ps;
   const uint32_t plb = (uint32_t)plane * es;       // bytes per plane
   const uint32_t spb = kNV * plb;                  // bytes per species
   const rsrc_t rin = make_rsrc((const T *)I.buf[in_idx] + (size_t)s * kNV * plane, spb);
@@ -1489,7 +1490,7 @@ __device__ __forceinline__ void plain_feq_cell(const InstDev &I, const FV<ST> &f
   for (int s = 0; s < S; ++s) {
     double a = 0, b = 0, cc = 0, d = 0;
     for (int i = 0; i < kNV; ++i) {
-      const double v = (double)f[(size_t)(s * kNV + i) * plane + cell];
+      const double v = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
       const double vx = sp[s].M[1 * kNV + i], vy = sp[s].M[2 * kNV + i], q = sp[s].M[3 * kNV + i];
       a += v;
       b = fma(v, vx, b);
@@ -1600,7 +1601,7 @@ __device__ __forceinline__ typename Stor<ST>::C plain_value(const InstDev &I, co
   int p = i;
   if (fx) p = I.sp[s].mirx[p];
   if (fy) p = I.sp[s].miry[p];
-  return f[(size_t)(s * kNV + p) * plane + (size_t)my * I.nx + mx];
+  return f[(size_t)(s * kNV + p) * I.ps + (size_t)my * I.nx + mx];
 }
 
 template <typename T>
@@ -1628,7 +1629,7 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   const FV<ST> f = fview<ST>(I, in_idx);
   const SpeciesDev &sp = I.sp[s];
   const double vx = sp.M[1 * kNV + i], vy = sp.M[2 * kNV + i];
-  const T fc = f[(size_t)si * plane + cell];
+  const T fc = f[(size_t)si * I.ps + cell];
   T C = T(0);
   if (vx != 0.0) {
     T w[5];
@@ -1650,15 +1651,15 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   T res;
   if (std::is_same<ST, float>::value && sr) {   // stochastic rounding (see sr_add)
     T d = C + (T)sp.omega * (feq - fc);
-    if (rkc) d = fma(alpha, (fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - fc) - d, d);
+    if (rkc) d = fma(alpha, (fview<ST>(I, fn_idx)[(size_t)si * I.ps + cell] - fc) - d, d);
     const uint32_t key = (uint32_t)cell * 0x9E3779B9u ^ (uint32_t)(si + 1) * 0x85EBCA6Bu ^
                          (uint32_t)__float_as_uint((float)fc);
     res = (T)sr_add((float)fc, (float)d, mix32(key));
   } else {
     res = fc + C + (T)sp.omega * (feq - fc);
-    if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * plane + cell] - res, res);
+    if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * I.ps + cell] - res, res);
   }
-  fview<ST>(I, out_idx).set((size_t)si * plane + cell, res);
+  fview<ST>(I, out_idx).set((size_t)si * I.ps + cell, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -1701,7 +1702,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
     for (int r = 0; r < kNV; ++r) {
       double acc = 0.0;
       for (int k = 0; k < kNV; ++k) acc = fma(sp.Minv[r * kNV + k], h[k], acc);
-      out.set((size_t)(s * kNV + r) * plane + cell, acc);
+      out.set((size_t)(s * kNV + r) * I.ps + cell, acc);
     }
   }
 }
@@ -1714,7 +1715,7 @@ __device__ __forceinline__ void dense_moments(const InstDev &I, const FV<ST> &f,
   const SpeciesDev &sp = I.sp[s];
   n = jx = jy = E = 0.0;
   for (int i = 0; i < kNV; ++i) {
-    const double v = (double)f[(size_t)(s * kNV + i) * plane + cell];
+    const double v = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
     n += v;
     jx = fma(v, sp.M[1 * kNV + i], jx);
     jy = fma(v, sp.M[2 * kNV + i], jy);
@@ -1796,7 +1797,7 @@ __global__ __launch_bounds__(256) void k_noneq(const InstDev *__restrict__ insts
   for (int r = 0; r < kNV; ++r) {
     double acc = 0.0;
     for (int k = 0; k < kNV; ++k) acc = fma(sp.Minv[r * kNV + k], h[k], acc);
-    dfv[r] = (double)f[(size_t)(which * kNV + r) * plane + cell] - acc;
+    dfv[r] = (double)f[(size_t)(which * kNV + r) * I.ps + cell] - acc;
   }
   for (int row = 4; row < kNV; ++row) {
     double acc = 0.0;
@@ -1852,7 +1853,7 @@ __global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ inst
   for (int r = 0; r < 4; ++r) {
     double acc = 0.0;
     for (int i = 0; i < kNV; ++i)
-      acc = fma(sp.M[rows[r] * kNV + i], (double)f[(size_t)(which * kNV + i) * plane + cell], acc);
+      acc = fma(sp.M[rows[r] * kNV + i], (double)f[(size_t)(which * kNV + i) * I.ps + cell], acc);
     mf[r] = acc;
   }
   const double hm = 0.5 * sp.m;
@@ -1969,7 +1970,7 @@ __global__ __launch_bounds__(256) void k_check(const InstDev *__restrict__ insts
   for (int s = 0; s < I.S; ++s) {
     double n = 0.0;
     for (int i = 0; i < kNV; ++i) {
-      const double v = (double)f[(size_t)(s * kNV + i) * plane + cell];
+      const double v = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
       bad |= !isfinite(v);
       n += v;
     }

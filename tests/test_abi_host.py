@@ -39,8 +39,12 @@ def test_workspace_bytes_is_positive_and_scales():
     assert b64 > 0 and b32 > 0 and b32 < b64
     # three f buffers at least
     assert b32 >= 3 * 3 * 16 * 64 * 64 * 4
-    big = D.dbm_workspace_bytes(D.Configs([W.reacting(n=128, steps=1)], "fp32"))
-    assert 3.5 < big / b32 < 4.5
+    # four times the cells: about four times the bytes (each plane of the f
+    # buffers also carries a fixed pad of a few KiB)
+    mid = D.dbm_workspace_bytes(D.Configs([W.reacting(n=256, steps=1)], "fp32"))
+    big = D.dbm_workspace_bytes(D.Configs([W.reacting(n=512, steps=1)], "fp32"))
+    assert 3.8 < big / mid < 4.2
+    assert big >= 3 * 3 * 16 * 512 * 512 * 4
 
 
 @pytest.mark.parametrize("bad,code", [
