@@ -790,6 +790,11 @@ __device__ __forceinline__ int rows_run(bool steady, int rows) {
 // shortens each wavefront's rows (small, latency-bound grids gain) at 16
 // more VGPRs (large, throughput-bound grids lose); the tuner picks.
 
+// FP32 chain-wavefront rows form their stencils before the row barrier (in
+// FP64 the extra live values would not fit in registers).
+#ifndef DBM_EARLY_STENCIL
+#define DBM_EARLY_STENCIL 1
+#endif
 // Halo distribution: LDS crossbar gather (1) or lane reads (0), per type.
 #ifndef DBM_GATHER_F32
 #define DBM_GATHER_F32 1
@@ -996,7 +1001,27 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     // chain wavefront: publish row k+1's moments, one barrier, then row k's
     // collision from the chain the chain wavefront formed during row k-1.
     if constexpr (!kPipe && !kCW) collide(k, c, sp, me, df);
-    if constexpr (kCW) {
+    // Chain wavefront, stencil first (kEarlyStencil): the stencils of row k
+    // and the carried rows' update are formed before the row's barrier, so
+    // they overlap the wait for the chain; the collision and the combine
+    // follow it.
+    constexpr bool kEarlyStencil = kCW && DBM_EARLY_STENCIL && sizeof(T) == 4;
+    // Row k's collision from the chain and moments in LDS, and the
+    // publication of row k+1's moments (from its values fn1) before it.
+    auto cw_collide = [&](const T *fn1, const T *oA, const T *oB, const T *oX, const T *oY) {
+      if (k + 1 < yend) publish(k + 1, fn1, me);
+      __syncthreads();
+      double(*cb)[kWave] = chn[k & 1];
+      const double ux = cb[0][lane], uy = cb[1][lane], Tst = cb[2][lane];
+      const double dn = cb[3 + s][lane];
+      // Row k's own moments are the ones this wavefront published for the
+      // chain (from the same values); only this wavefront writes its slots.
+      double(*mk)[kWave] = mom[k & 1];
+      const double n0 = mk[0 * S + s][lane], jx0 = mk[1 * S + s][lane];
+      const double jy0 = mk[2 * S + s][lane], E0 = mk[3 * S + s][lane];
+      collision_delta<T>(I, me, oA, oB, oX, oY, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, df);
+    };
+    if constexpr (kCW && !kEarlyStencil) {
       if (k + 1 < yend) {
         T fn1[kNV];
 #pragma unroll
@@ -1063,11 +1088,12 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       if constexpr (!kEarlyHalo)
         if (writer && (!kSteady || k < yend)) bout.store((uint32_t)(rk + col), i, res[i]);
     };
-#pragma unroll
-    for (int i = 0; i < kNV; ++i) {
+    // Plane i: f (out) and its value plus advection increment (with
+    // stochastic rounding the increment alone); advances the carried rows.
+    auto advect = [&](int i, T &f) -> T {
       const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
-      const T f = c[i];
-      T a = kSR ? T(0) : f;   // with stochastic rounding: the increment alone
+      f = c[i];
+      T a = kSR ? T(0) : f;
       // x: NND difference from adjacent lanes.
       // Differences and limited slopes of the neighbouring lanes are the
       // same quantities one lane over, so each is formed once and shifted.
@@ -1117,7 +1143,24 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
       } else {
         c[i] = carry(fnew);
       }
-      finish(i, a, f);
+      return a;
+    };
+    if constexpr (kEarlyStencil) {
+      T oA[4], oB[4], oX[4], oY[4];
+      orbit_parts<T>(c, oA, oB, oX, oY);
+      T acc[kNV], fk[kNV];
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) acc[i] = advect(i, fk[i]);
+      cw_collide(c, oA, oB, oX, oY);   // c now holds row k+1's values
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) finish(i, acc[i], fk[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) {
+        T f;
+        const T a = advect(i, f);
+        finish(i, a, f);
+      }
     }
     // FP32: one masked block of stores per row (lanes past nx hold wrapped
     // or clamped copies and write nothing), so that the row is one basic
