@@ -41,8 +41,8 @@ UNIT = "cell-species updates/s"
 # workload, with the hash of the kernel source they were taken at.  A changed
 # kernel source makes the entry stale and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "c1/fp32": {"source": "667c9b8775dd6dcf", "bytes_per_launch": 26491708},
-    "c4/fp32": {"source": "667c9b8775dd6dcf", "bytes_per_launch": 9618330635},
+    "c1/fp32": {"source": "4137a3cc59f9610e", "bytes_per_launch": 26479549},
+    "c4/fp32": {"source": "4137a3cc59f9610e", "bytes_per_launch": 9585390037},
 }
 
 
