@@ -26,6 +26,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -38,19 +39,32 @@ UNIT = "cell-species updates/s"
 
 # HBM bytes per launch of the one-pass stage kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs (profiles/fused_stage_traffic.md), keyed by
-# workload, with the hash of the kernel source they were taken at.  A changed
-# kernel source makes the entry stale and `traffic` is reported as null.
+# workload, with the hash of the kernel code they were taken at (source
+# without comments, see code_text).  Changed kernel code makes the entry stale
+# and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "c1/fp32": {"source": "4137a3cc59f9610e", "bytes_per_launch": 26479549},
-    "c4/fp32": {"source": "4137a3cc59f9610e", "bytes_per_launch": 9585390037},
+    "c1/fp32": {"source": "8d6fdfe50da2e1b8", "bytes_per_launch": 26479549},
+    "c4/fp32": {"source": "8d6fdfe50da2e1b8", "bytes_per_launch": 9585390037},
 }
+
+
+def code_text(src: str) -> str:
+    """Source text without // comments and blank lines, trailing spaces
+    stripped: what the compiler sees of the kernel, so that a comment edit
+    does not mark the traffic measurement stale."""
+    lines = []
+    for line in src.splitlines():
+        line = re.sub(r"//.*$", "", line).rstrip()
+        if line:
+            lines.append(line)
+    return "\n".join(lines)
 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in ("dbm_kernels.hip", "dbm_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2006_15932_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2006_15932_amd", "csrc", f), encoding="utf-8") as fh:
+            h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -2,8 +2,10 @@
 //
 // Data layout in HBM (per instance): three distribution buffers, each
 // [S][16][ny][nx] in the storage precision (float for FP32-bulk, double for
-// FP64), x fastest, so every velocity plane is a dense 2-D array and a
-// wavefront's 64 lanes read 64 consecutive cells of one plane per load.
+// FP64; FP32X: all FP32 parts, then all bf16 parts), x fastest, so every
+// velocity plane is a dense 2-D array and a wavefront's 64 lanes read 64
+// consecutive cells of one plane per load.  Consecutive planes are InstDev.ps
+// elements apart: nx*ny plus a pad of 17 x 256 bytes (plane_stride).
 //
 // The one-pass stage kernel (k_fused_stage) gives each workgroup a tile of 64
 // columns (one per lane, 128-byte aligned) by `rows` rows, one wavefront per
