@@ -251,12 +251,15 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
 // f + d rounded to FP32 stochastically with the 8 random bits in the low byte
 // of u8: the exact remainder of the nearest sum (exact when |f| >= |d|) plus
 // a dither uniform over 256 levels in (-ulp/2, ulp/2), rounded to nearest.
+// With E the power of two of sm's exponent (ulp = E 2^-23) the dither is
+// E t, t = (u + 1/2) 2^-31 - 2^-24 formed exactly by one multiply-add, and
+// er + E t is exact in its multiply-add too.
 __device__ __forceinline__ float sr_add(float f, float d, uint32_t u8) {
   const float sm = f + d;
   const float er = d - (sm - f);
-  const float ulp = __uint_as_float(__float_as_uint(sm) & 0x7f800000u) * 0x1p-23f;
-  const float u = (float)(u8 & 0xffu);
-  return sm + (er + fma(u, ulp * 0x1p-8f, ulp * (0x1p-9f - 0.5f)));
+  const float E = __uint_as_float(__float_as_uint(sm) & 0x7f800000u);
+  const float t = fma((float)(u8 & 0xffu), 0x1p-31f, 0x1p-32f - 0x1p-24f);
+  return sm + fma(E, t, er);
 }
 
 // Element access to one buffer of n values (generic kernels).
