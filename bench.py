@@ -276,7 +276,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); "
+        print("bench.py: one GPU only (the library has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.mode == "traffic":

@@ -1,0 +1,33 @@
+"""Host-side checks of the benchmark driver (no GPU): the one-GPU guard and
+the kernel-code hash that keys the stored traffic measurements."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused_before_any_gpu_work():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_code_text_drops_comments_and_blank_lines_only():
+    src = "int a; // note\n\n   // whole-line comment\n  b = a * 2;   \nc();"
+    assert bench.code_text(src) == "int a;\n  b = a * 2;\nc();"
+    # a comment edit leaves the hash input unchanged, a code edit does not
+    assert bench.code_text("x = 1; // old") == bench.code_text("x = 1; // new words")
+    assert bench.code_text("x = 1;") != bench.code_text("x = 2;")
+
+
+def test_kernel_hash_is_stable_and_stored_entries_are_well_formed():
+    h = bench.kernel_source_hash()
+    assert h == bench.kernel_source_hash() and len(h) == 16
+    for key, entry in bench.MEASURED_TRAFFIC.items():
+        assert key in ("c1/fp32", "c4/fp32")
+        assert len(entry["source"]) == 16 and entry["bytes_per_launch"] > 0
