@@ -1066,18 +1066,18 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     const T om = Tab<T>::omega(me);
     T res[kNV];
     // Stochastic rounding: the increment d is formed apart from f and the
-    // sum rounded once, with 8 random bits per value from four hashes per
-    // lane and row.
+    // sum rounded once, with 8 random bits per value from four independent
+    // hashes per lane and row of one key (each key step one xor-add).
     constexpr bool kSR = SR && std::is_same<ST, float>::value;
     uint32_t rb[4];
     if constexpr (kSR) {
       uint32_t key = (uint32_t)(rk + col) * 0x9E3779B9u ^ (uint32_t)(s + 1) * 0x85EBCA6Bu;
 #pragma unroll
-      for (int i = 0; i < kNV; ++i) key ^= __float_as_uint(c[i]) + (uint32_t)i * 0x27D4EB2Fu;
+      for (int i = 0; i < kNV; ++i) key = (key ^ __float_as_uint(c[i])) + (uint32_t)i * 0x27D4EB2Fu;
       rb[0] = mix32(key);
-      rb[1] = mix32(rb[0] ^ 0x68E31DA4u);
-      rb[2] = mix32(rb[1] ^ 0xB5297A4Du);
-      rb[3] = mix32(rb[2] ^ 0x1B56C4E9u);
+      rb[1] = mix32(key ^ 0x68E31DA4u);
+      rb[2] = mix32(key ^ 0xB5297A4Du);
+      rb[3] = mix32(key ^ 0x1B56C4E9u);
     }
     auto finish = [&](int i, T a, T f) {
       if constexpr (kSR) {
