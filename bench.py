@@ -43,8 +43,8 @@ UNIT = "cell-species updates/s"
 # without comments, see code_text).  Changed kernel code makes the entry stale
 # and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
-    "c1/fp32": {"source": "b96030ac81f214a4", "bytes_per_launch": 26489788},
-    "c4/fp32": {"source": "b96030ac81f214a4", "bytes_per_launch": 9556785826},
+    "c1/fp32": {"source": "a12b2d61298798f0", "bytes_per_launch": 26489788},
+    "c4/fp32": {"source": "a12b2d61298798f0", "bytes_per_launch": 9607444038},
 }
 
 

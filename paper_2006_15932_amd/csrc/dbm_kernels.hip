@@ -754,6 +754,14 @@ __device__ __forceinline__ int xcd_remap(int v, int n) {
 #endif
 constexpr int kPrefetch = DBM_PREFETCH;
 static_assert(kPrefetch >= 2, "the prefetch ring needs two or more slots");
+// Rows of loads in flight per wavefront in the one-pass kernel: three for the
+// four-species FP32 Euler form (1% faster on the 4096^2 and 2048^2 shear
+// layers than two), kPrefetch elsewhere (three slowed the Runge-Kutta and
+// stochastic-rounding forms by 7-11% through register pressure).
+template <typename ST, int S, bool RKC, bool PIPE, bool SR, bool CW>
+constexpr int kRing = (std::is_same<ST, float>::value && S == 4 && !RKC && !PIPE && !SR && !CW)
+                          ? (kPrefetch > 3 ? kPrefetch : 3)
+                          : kPrefetch;
 
 // The 12 planes with a nonzero v_x, in plane order, and the halo columns each
 // needs: x0-1 and x0+64 always, and x0-2 (v_x > 0) or x0+65 (v_x < 0).
@@ -819,6 +827,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
                                            double (*mom)[4 * S][kWave],
                                            double (*chn)[kChainRows<S, CW>][kWave]) {
   typedef typename Stor<ST>::C T;                  // arithmetic type
+  constexpr int kPf = kRing<ST, S, RKC, PIPE, SR, CW>;   // rows of loads in flight
   const int lane = threadIdx.x & (kWave - 1);
   const int nx = I.nx, ny = I.ny, bcy = I.bcy;
   // One set of buffer resources per species and buffer (its 16 planes,
@@ -940,8 +949,8 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   // Row k consumes ring slot d and refills the slot freed by row k-1 with the
   // values of row k+D-1, so D rows of loads are in flight.  (Issuing the
   // first slots before the first collision measured slower than after it.)
-  T ring[kPrefetch][kNV];
-  T hring[kPrefetch];
+  T ring[kPf][kNV];
+  T hring[kPf];
   constexpr bool kPipe = PIPE && sizeof(T) == 4;
   constexpr bool kCW = CW;
   static_assert(!(kPipe && kCW), "the chain wavefront replaces the row pipeline");
@@ -957,7 +966,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   }
   start_state();
 #pragma unroll
-  for (int d = 0; d < kPrefetch - 1; ++d)
+  for (int d = 0; d < kPf - 1; ++d)
     if (y0 + d < yend) issue(y0 + d, ring[d], hring[d]);
 
   // kSteady (FP64 arithmetic): the loop body has no conditional loads or
@@ -968,7 +977,7 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
   // measured faster.
   constexpr bool kSteady = kSteadyRows<T>;
   auto row = [&](int k, const T *cur, const T hcur, T *refill, T &hrefill) {
-    if (kSteady || k + kPrefetch - 1 < yend) issue(k + kPrefetch - 1, refill, hrefill);
+    if (kSteady || k + kPf - 1 < yend) issue(k + kPf - 1, refill, hrefill);
     const int rk = k * nx;
     const int rkn = k < ny ? rk : (ny - 1) * nx;   // f^n row (a row past the grid: not stored)
     SpC *sp = launder(as_const(I.sp));
@@ -1182,12 +1191,12 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     }
   };
 
-  for (int k = y0; k < yend; k += kPrefetch) {
+  for (int k = y0; k < yend; k += kPf) {
 #pragma unroll
-    for (int d = 0; d < kPrefetch; ++d) {
+    for (int d = 0; d < kPf; ++d) {
       if (kSteady || k + d < yend)
-        row(k + d, ring[d], hring[d], ring[(d + kPrefetch - 1) % kPrefetch],
-            hring[(d + kPrefetch - 1) % kPrefetch]);
+        row(k + d, ring[d], hring[d], ring[(d + kPf - 1) % kPf],
+            hring[(d + kPf - 1) % kPf]);
     }
   }
 }
