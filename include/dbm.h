@@ -144,18 +144,43 @@ int dbm_destroy(dbm_handle h);
 int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
                    const double *uy, const double *T);
 
-/* Write / read the raw distribution [S][16][ny][nx] (FP64 host arrays),
- * rounded to / widened from the storage precision. */
+/* Write / read the distribution [S][16][ny][nx] (FP64 host arrays), rounded
+ * to / widened from the storage precision.  With OM storage (FP32-bulk, see
+ * DBM_OPT_STORAGE) dbm_set_f also sets the storage reference from f (the least
+ * density of each species and the least temperature) and stores f in that
+ * representation; a get/set round trip then agrees to FP32 rounding of the
+ * stored values, not always bit for bit: bit-exact checkpoints use
+ * dbm_save_state / dbm_load_state. */
 int dbm_set_f(dbm_handle h, int inst, const double *f);
 int dbm_get_f(dbm_handle h, int inst, double *f);
 
-/* Advance every instance by nsteps time steps.  Asynchronous on the stream
- * unless the non-finite check is enabled (then DBM_ERR_NONFINITE may be
- * returned after a synchronisation). */
+/* Checkpoint and restart, bit for bit: the state of instance inst (its
+ * distribution exactly as stored, the reference of OM storage and the step
+ * counter of stochastic rounding) as an opaque host blob of
+ * dbm_state_bytes() bytes (0 on a bad handle or index).  dbm_load_state
+ * accepts only a blob saved by a handle of the same precision, storage
+ * representation (DBM_OPT_STORAGE), species count and grid size
+ * (DBM_ERR_ARG otherwise); the caller owns both host buffers.  Synchronise. */
+size_t dbm_state_bytes(dbm_handle h, int inst);
+int dbm_save_state(dbm_handle h, int inst, void *dst, size_t bytes);
+int dbm_load_state(dbm_handle h, int inst, const void *src, size_t bytes);
+
+/* Advance every instance by nsteps time steps of the discrete Boltzmann
+ * equation, Eq.(3): the right-hand side is the NND upwind convection -v.grad f
+ * plus the collision, reaction and force terms of Eqs.(4)-(6), and the time
+ * discretisation is forward Euler (the scheme of the paper's simulation
+ * section, with NND in space) or third-order TVD Runge-Kutta, per
+ * dbm_config.time_scheme.  Asynchronous on the stream unless the non-finite
+ * check is enabled (then DBM_ERR_NONFINITE may be returned after a
+ * synchronisation).  nsteps < 0: DBM_ERR_ARG; nsteps == 0 does nothing. */
 int dbm_step(dbm_handle h, int nsteps);
 
-/* Macroscopic fields of instance inst: rho^s = m^s n^s [S][ny][nx] and the
- * mixture ux, uy, T [ny][nx] (any pointer may be NULL).  Synchronises. */
+/* Macroscopic fields of instance inst, from the moments of f that the
+ * collision conserves (the statement under Eq.(6), with the kinetic moments of
+ * Eqs.(8)-(10)): rho^s = m^s n^s with n^s = sum_i f_i^s [S][ny][nx]; the
+ * mixture velocity u = sum_s m^s sum_i f_i^s v_i / rho and temperature
+ * T = (sum_s m^s sum_i f_i^s (v_i^2 + eta_i^2) - rho u^2) / sum_s (D + I^s) n^s
+ * [ny][nx] (any pointer may be NULL).  Synchronises. */
 int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, double *T);
 
 /* Nonequilibrium measures of Eqs.(17)-(20), taken against f^eq(n^s, u, T):
@@ -203,6 +228,21 @@ enum {
                                from the cell, species and state, so runs are
                                deterministic); DBM_ERR_UNSUPPORTED for other
                                precisions and with the split form */
+  DBM_OPT_STORAGE = 12,     /* FP32-bulk representation of f in the buffers:
+                               0 (default) OM storage wherever the one-pass
+                               path runs its full form without the row
+                               pipeline: per cell and species the A-block
+                               moments (n, E and two more) of f - fref and
+                               the orbit components B, X, Y of f, fref =
+                               f^eq(least n^s, 0, least T) over the cells,
+                               fixed when the fields or f are set; 1 the 16
+                               values f_i themselves.
+                               Both are 16 FP32 values per cell and species;
+                               OM storage rounds mass and energy relative to
+                               their deviation from fref and momentum
+                               relative to itself.  Setting it (or an option
+                               that excludes OM storage) converts the state
+                               in place; get: 0 OM storage in use, 1 f */
   DBM_OPT_CHAIN_WAVE = 11   /* one-pass path, nspecies <= 3: one more wavefront
                                per workgroup forms each row's mixture chain
                                (u, T, reaction) while the species' wavefronts
@@ -222,12 +262,14 @@ int dbm_time_stage_kernel(dbm_handle h, int reps, double *ms_per_launch);
 
 /* Measurement reference, not part of the method: copies `bytes` (a multiple
  * of 16, both pointers device memory aligned to 16 bytes, not overlapping)
- * from src to dst with a grid-stride streaming copy of 16-byte words on
- * `grid` workgroups of 256 threads, `reps` times after one warm-up copy, on
- * hip_stream (NULL = default stream), and returns the mean duration of one
- * copy in milliseconds from HIP events.  The achievable HBM rate is then
- * 2 bytes / time.  Synchronises; DBM_ERR_ARG on bad arguments. */
-int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
+ * from src to dst with a grid-stride streaming copy of 16-byte words (each
+ * thread keeping `words` = 1, 2, 4 or 8 of them in flight per iteration,
+ * non-temporal stores) on `grid` workgroups of 256 threads, `reps` times
+ * after one warm-up copy, on hip_stream (NULL = default stream), and returns
+ * the mean duration of one copy in milliseconds from HIP events.  The
+ * achievable HBM rate is then 2 bytes / time.  Synchronises; DBM_ERR_ARG on
+ * bad arguments. */
+int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int words, int reps,
                   void *hip_stream, double *ms_per_copy);
 
 /* Thread-local description of the last error. */

@@ -17,15 +17,22 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
+void set_reference(SpeciesDev &sp, double n_ref, double T_ref);
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, const InstDev *insts,
-                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
-                        int out_idx, double alpha, double beta, hipStream_t st);
-hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw,
+                        bool cw, bool om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
+                        int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
+                        double beta, hipStream_t st);
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
                            int *waves_per_cu);
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
-                        bool sr, hipStream_t st);
+                        bool sr, uint32_t *ctr, hipStream_t st);
+hipError_t launch_widen_om(const InstDev *insts, int inst, size_t cells, int b, int s, int i,
+                           double *dst, hipStream_t st);
+hipError_t launch_pack_om(const InstDev *insts, int inst, size_t cells, const double *lo,
+                          const double *hi, int b, hipStream_t st);
+hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, bool to_om,
+                             hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *insts, int inst, size_t cells,
                        const double *fields, int out_idx, hipStream_t st);
 hipError_t launch_moments(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
@@ -48,7 +55,8 @@ hipError_t launch_check(int prec, const InstDev *insts, int inst, size_t cells, 
                         int *flag, hipStream_t st);
 hipError_t launch_dpp_probe(int *out, hipStream_t st);
 hipError_t launch_delay(double microseconds, hipStream_t st);
-hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipStream_t st);
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, int words,
+                         hipStream_t st);
 }  // namespace dbm
 
 using namespace dbm;
@@ -76,9 +84,11 @@ constexpr int kTilesPerRowStride = 64;  // columns per tile (one per lane)
 
 int tiles_x(int nx) { return (nx + kTilesPerRowStride - 1) / kTilesPerRowStride; }
 
+constexpr int kProbeInts = 640;   // DPP lane-layout probe results
+
 struct Layout {
   size_t sp_off = 0, inst_off = 0, tile_off = 0, part_off = 0, tot_off = 0, flag_off = 0,
-         probe_off = 0;
+         probe_off = 0, ctr_off = 0;
   size_t tile_cap = 0;
   std::vector<size_t> buf_off[3], scratch_off;
   size_t total = 0;
@@ -186,7 +196,10 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   L.flag_off = off;
   off = align_up(off + sizeof(int));
   L.probe_off = off;
-  off = align_up(off + sizeof(int) * 512);
+  off = align_up(off + sizeof(int) * kProbeInts);
+  // step counters of stochastic rounding: [0..1] the run's, [2..3] timing launches'
+  L.ctr_off = off;
+  off = align_up(off + sizeof(uint32_t) * 4);
   for (int b = 0; b < 3; ++b) L.buf_off[b].resize(ninst);
   L.scratch_off.resize(ninst);
   for (int k = 0; k < ninst; ++k) {
@@ -215,6 +228,7 @@ std::mutex g_tune_mu;
 std::map<TuneKey, std::pair<int, int>> g_tune_cache;  // -> (rows, form)
 std::mutex g_probe_mu;
 int g_probe_state = 0;  // 0 unknown, 1 ok, -1 failed
+int g_probe_om = 0;     // broadcasts of the OM halo transform: 1 ok, -1 failed
 
 }  // namespace
 
@@ -223,6 +237,11 @@ struct dbm_s {
   bool fp32 = false;     // FP32-bulk
   int prec = DBM_FP64;  // DBM_FP64 | DBM_FP32_BULK | DBM_FP32X
   int sr = 0;           // DBM_OPT_ROUNDING: 1 stochastic rounding of FP32 stores
+  int om_opt = 0;       // DBM_OPT_STORAGE: 0 OM storage where available, 1 f itself
+  bool om = false;      // the buffers (every instance) hold OM storage
+  std::vector<SpeciesDev> tabs;  // host copy of the species tables (OM reference)
+  std::vector<std::vector<double>> ref_n;  // OM reference per instance: n_ref^s ...
+  std::vector<double> ref_T;               // ... and T_ref
   std::vector<dbm_config> cfg;
   std::vector<std::vector<dbm_species>> species;
   std::vector<dbm_reaction> reaction;
@@ -245,13 +264,17 @@ struct dbm_s {
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
   // workgroups resident on the device, per form
-  int resident = 0, resident_split = 0, resident_cw = 0;
-  int grid_cap() const { return split ? resident_split : (cw ? resident_cw : resident); }
+  int resident = 0, resident_split = 0, resident_cw = 0, resident_om = 0, resident_om_cw = 0;
+  int grid_cap() const {
+    if (om) return cw ? resident_om_cw : resident_om;
+    return split ? resident_split : (cw ? resident_cw : resident);
+  }
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   long long since_check = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 
   const InstDev *d_inst() const { return (const InstDev *)(ws + L.inst_off); }
+  uint32_t *d_ctr(bool timing) const { return (uint32_t *)(ws + L.ctr_off) + (timing ? 2 : 0); }
   const Tile *d_tiles() const { return (const Tile *)(ws + L.tile_off); }
   size_t cells(int k) const { return (size_t)cfg[k].nx * cfg[k].ny; }
   size_t ps(int k) const { return pstride(cfg[k]); }
@@ -287,30 +310,32 @@ int upload_tiles(dbm_handle h) {
   return DBM_OK;
 }
 
-// One stage: out = alpha f^n + beta (f + dt L(f)), on stream st.
+// One stage: out = alpha f^n + beta (f + dt L(f)), on stream st.  Timing
+// launches (timing) advance a step counter of their own, so that they leave
+// the run's stochastic rounding unchanged.
 int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alpha, double beta,
-                  bool rkc, hipStream_t st) {
+                  bool rkc, hipStream_t st, bool timing = false) {
+  uint32_t *ctr = h->d_ctr(timing);
   if (use_fused(h)) {
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                          h->d_inst(),
-                          h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx, alpha, beta, st));
+      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw, h->om,
+                          ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx,
+                          alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
         HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                          h->d_inst(),
-                            h->d_tiles() + b, nt, grid, in_idx, fn_idx, out_idx, alpha, beta,
-                            st));
+                            h->om, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx, fn_idx,
+                            out_idx, alpha, beta, st));
       }
     }
   } else {
     for (int k = 0; k < h->ninst; ++k)
       HIPCHK(launch_plain(h->prec, h->d_inst(), k, h->cells(k), h->S, in_idx, fn_idx, out_idx,
-                          alpha, beta, rkc, h->sr != 0, st));
+                          alpha, beta, rkc, h->sr != 0, ctr, st));
   }
   return DBM_OK;
 }
@@ -334,8 +359,9 @@ int enqueue_step(dbm_handle h, int &parity, hipStream_t st) {
 // The stage launch a step is made of (Euler) or that dominates it (RK3,
 // stages 2-3), writing only a spare buffer.
 int enqueue_timed_stage(dbm_handle h, hipStream_t st) {
-  if (h->scheme == DBM_EULER) return enqueue_stage(h, h->cur, h->cur, 1 - h->cur, 0.0, 1.0, false, st);
-  return enqueue_stage(h, 1, 0, 2, 0.75, 0.25, true, st);
+  if (h->scheme == DBM_EULER)
+    return enqueue_stage(h, h->cur, h->cur, 1 - h->cur, 0.0, 1.0, false, st, true);
+  return enqueue_stage(h, 1, 0, 2, 0.75, 0.25, true, st, true);
 }
 
 // Mean launch time over reps back-to-back launches; med (optional) gets the
@@ -394,7 +420,8 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    ((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr};
+                    (((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 2 +
+                        (h->om ? 1 : 0)};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -418,8 +445,8 @@ int ensure_tuned(dbm_handle h) {
       h->split = f == 1;
       // the row pipeline (pp 1) exists for the FP32 full form, the chain
       // wavefront (pp 2) for the full form with S <= 3
-      const bool can_pipe = h->fp32 && f == 0;
-      const bool can_cw = f == 0 && h->S <= 3 && h->resident_cw > 0;
+      const bool can_pipe = h->fp32 && f == 0 && !h->om;
+      const bool can_cw = f == 0 && h->S <= 3 && (h->om ? h->resident_om_cw : h->resident_cw) > 0;
       for (int pp = 0; pp < 3; ++pp) {
         if (pp == 1 && (!can_pipe || h->pipe_opt == 1)) continue;
         if (pp == 2 && (!can_cw || h->cw_opt == 1)) continue;
@@ -457,7 +484,9 @@ int ensure_tuned(dbm_handle h) {
   if (h->tile_rows_opt > 0) {  // fixed rows: the form and pipeline the options ask for
     form = h->split_opt == 2 ? 1 : 0;
     if (form == 0 && h->fp32 && h->pipe_opt == 2) form = 2;
-    if (form == 0 && h->cw_opt == 2 && h->S <= 3 && h->resident_cw > 0) form = 4;
+    if (form == 0 && h->cw_opt == 2 && h->S <= 3 &&
+        (h->om ? h->resident_om_cw : h->resident_cw) > 0)
+      form = 4;
   }
   if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) != 0) ||
       h->pipe != ((form & 2) != 0) || h->cw != ((form & 4) != 0)) {
@@ -516,7 +545,7 @@ int run_probe(dbm_handle h) {
   std::lock_guard<std::mutex> g(g_probe_mu);
   if (g_probe_state != 0) return DBM_OK;
   int *d = (int *)(h->ws + h->L.probe_off);
-  int out[512];
+  int out[kProbeInts];
   HIPCHK(launch_dpp_probe(d, h->stream));
   HIPCHK(hipMemcpyAsync(out, d, sizeof(out), hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -532,6 +561,86 @@ int run_probe(dbm_handle h) {
       ok &= gl == (l == 63 ? 0 : l + 2);
     }
   g_probe_state = ok ? 1 : -1;
+  bool om_ok = true;   // row and quad broadcasts of the OM halo transform
+  for (int l = 0; l < 64; ++l) {
+    om_ok &= out[512 + l] == 16 * (l / 16) + 4;
+    om_ok &= out[576 + l] == 4 * (l / 4) + 2;
+  }
+  g_probe_om = om_ok ? 1 : -1;
+  return DBM_OK;
+}
+
+// Whether the options ask for OM storage: FP32-bulk on the one-pass path in
+// its full form without the row pipeline, OM storage not switched off, and
+// the halo transform's lane broadcasts verified on this device.
+bool want_om(dbm_handle h) {
+  return h->prec == DBM_FP32_BULK && h->om_opt == 0 && use_fused(h) && h->split_opt != 2 &&
+         h->pipe_opt != 2 && g_probe_om > 0 && h->resident_om > 0;
+}
+
+int upload_inst(dbm_handle h) {
+  for (auto &d : h->inst) d.om = h->om ? 1 : 0;
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.inst_off, h->inst.data(), sizeof(InstDev) * h->ninst,
+                        hipMemcpyHostToDevice, h->stream));
+  return DBM_OK;
+}
+
+int upload_tables(dbm_handle h, int inst) {
+  const size_t off = h->L.sp_off + sizeof(SpeciesDev) * (size_t)inst * h->S;
+  HIPCHK(hipMemcpyAsync(h->ws + off, h->tabs.data() + (size_t)inst * h->S,
+                        sizeof(SpeciesDev) * h->S, hipMemcpyHostToDevice, h->stream));
+  return DBM_OK;
+}
+
+// Bring every instance's current buffer into the representation the options
+// ask for (FP32 f <-> OM storage, in place; FP64 arithmetic per cell).
+int sync_storage(dbm_handle h) {
+  const bool want = want_om(h);
+  if (want == h->om) return DBM_OK;
+  for (int k = 0; k < h->ninst; ++k)
+    HIPCHK(launch_convert_om(h->d_inst(), k, h->cells(k), h->cur, want, h->stream));
+  h->om = want;
+  int rc = upload_inst(h);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->rows = 0;
+  h->tiles.clear();
+  clear_graphs(h);
+  return DBM_OK;
+}
+
+// OM storage reference of instance inst: an equilibrium at rest with the
+// least density of each species and the least temperature of the initial
+// state (deviations stay non-negative and a species absent somewhere keeps no
+// offset); non-finite or negative entries are taken as 0 (no offset).
+int set_om_reference(dbm_handle h, int inst, const std::vector<double> &n_min, double T_min) {
+  std::vector<double> n(n_min);
+  for (auto &v : n)
+    if (!std::isfinite(v) || v < 0.0) v = 0.0;
+  const double T = (std::isfinite(T_min) && T_min > 0.0) ? T_min : 0.0;
+  for (int s = 0; s < h->S; ++s) set_reference(h->tabs[(size_t)inst * h->S + s], n[s], T);
+  h->ref_n[inst] = n;
+  h->ref_T[inst] = T;
+  return upload_tables(h, inst);
+}
+
+// Checkpoint blob: this header, then the instance's current f buffer as
+// stored (S x 16 planes of stride ps in the storage precision, FP32X with its
+// residual planes), so that a restart continues bit for bit.
+struct StateHeader {
+  uint64_t magic;
+  int32_t prec, om, S, nx, ny, sr;
+  uint64_t buffer_bytes;
+  double ref_n[kMaxSpecies], ref_T;
+  uint32_t ctr[2];
+};
+constexpr uint64_t kStateMagic = 0x4554415453424D44ULL;   // "DBMSTATE" in little-endian bytes
+size_t buffer_bytes(dbm_handle h, int inst) {
+  return (size_t)h->S * kNV * h->ps(inst) * esize(h->cfg[inst]);
+}
+
+int reset_counters(dbm_handle h) {
+  HIPCHK(hipMemsetAsync(h->ws + h->L.ctr_off, 0, sizeof(uint32_t) * 4, h->stream));
   return DBM_OK;
 }
 
@@ -577,6 +686,9 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     return fail(DBM_ERR_WORKSPACE, "workspace too small: need " + std::to_string(L.total) +
                                        " bytes");
   dbm_s *h = new dbm_s();
+  h->tabs = tabs;
+  h->ref_n.assign(ninst, std::vector<double>(cfgs[0].nspecies, 0.0));
+  h->ref_T.assign(ninst, 0.0);
   h->ninst = ninst;
   h->S = cfgs[0].nspecies;
   h->fp32 = cfgs[0].precision == DBM_FP32_BULK;
@@ -674,13 +786,19 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
   if ((rc = run_probe(h))) return bail(rc);
   if (g_probe_state < 0) h->fused_ok = false;
   if (h->fused_ok) {
-    int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, dev = 0;
+    int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, per_cu_om = 0, per_cu_om_cw = 0, dev = 0;
     hipDeviceProp_t prop;
     const bool rk3 = h->scheme == DBM_TVD_RK3;
-    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, &per_cu)) != hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, false, &per_cu_split)) !=
+    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, false, &per_cu)) !=
             hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, &per_cu_cw)) != hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, false, false, &per_cu_split)) !=
+            hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, false, &per_cu_cw)) !=
+            hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, true, &per_cu_om)) !=
+            hipSuccess ||
+        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, true, &per_cu_om_cw)) !=
+            hipSuccess ||
         (e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
       return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
@@ -688,7 +806,14 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     h->resident = round_xcd(per_cu * prop.multiProcessorCount);
     h->resident_split = round_xcd(per_cu_split * prop.multiProcessorCount);
     h->resident_cw = per_cu_cw > 0 ? round_xcd(per_cu_cw * prop.multiProcessorCount) : 0;
+    h->resident_om = per_cu_om > 0 ? round_xcd(per_cu_om * prop.multiProcessorCount) : 0;
+    h->resident_om_cw =
+        per_cu_om_cw > 0 ? round_xcd(per_cu_om_cw * prop.multiProcessorCount) : 0;
   }
+  h->om = want_om(h);
+  if ((rc = upload_inst(h)) || (rc = reset_counters(h))) return bail(rc);
+  if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
+    return bail(fail(DBM_ERR_HIP, std::string("set-up: ") + hipGetErrorString(e)));
   *out = h;
   return DBM_OK;
 }
@@ -710,6 +835,15 @@ int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
   if (rc) return rc;
   if (!n_sp || !ux || !uy || !T) return fail(DBM_ERR_ARG, "NULL field array");
   const size_t cells = h->cells(inst), S = h->S;
+  if (h->prec == DBM_FP32_BULK) {   // OM storage reference: least n^s and T, at rest
+    std::vector<double> nm(S, HUGE_VAL);
+    double tm = HUGE_VAL;
+    for (size_t s = 0; s < S; ++s)
+      for (size_t c = 0; c < cells; ++c) nm[s] = std::fmin(nm[s], n_sp[s * cells + c]);
+    for (size_t c = 0; c < cells; ++c) tm = std::fmin(tm, T[c]);
+    if ((rc = set_om_reference(h, inst, nm, tm))) return rc;
+  }
+  if ((rc = reset_counters(h))) return rc;
   double *stage = (double *)h->inst[inst].scratch;
   HIPCHK(hipMemcpyAsync(stage, n_sp, sizeof(double) * S * cells, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(stage + S * cells, ux, sizeof(double) * cells, hipMemcpyHostToDevice, h->stream));
@@ -726,9 +860,51 @@ int dbm_set_f(dbm_handle h, int inst, const double *f) {
   if (!f) return fail(DBM_ERR_ARG, "NULL f");
   const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV, ps = h->ps(inst);
   void *dst = h->inst[inst].buf[h->cur];
+  if (h->prec == DBM_FP32_BULK) {
+    // OM storage reference from f: least density of each species and least
+    // mixture temperature (moments n, j, E of every cell, FP64).
+    const int S = h->S;
+    std::vector<double> nm(S, HUGE_VAL);
+    double tm = HUGE_VAL;
+    for (size_t c = 0; c < cells; ++c) {
+      double rho = 0, px = 0, py = 0, e = 0, kn = 0;
+      for (int s = 0; s < S; ++s) {
+        const SpeciesDev &sp = h->tabs[(size_t)inst * S + s];
+        double n = 0, jx = 0, jy = 0, E = 0;
+        for (int i = 0; i < kNV; ++i) {
+          const double v = f[((size_t)s * kNV + i) * cells + c];
+          n += v;
+          jx += v * sp.M[1 * kNV + i];
+          jy += v * sp.M[2 * kNV + i];
+          E += v * sp.M[3 * kNV + i];
+        }
+        nm[s] = std::fmin(nm[s], n);
+        rho += sp.m * n;
+        px += sp.m * jx;
+        py += sp.m * jy;
+        e += sp.m * E;
+        kn += sp.K * n;
+      }
+      if (rho != 0.0 && kn != 0.0) tm = std::fmin(tm, (e - (px * px + py * py) / rho) / kn);
+    }
+    if ((rc = set_om_reference(h, inst, nm, tm))) return rc;
+  }
+  if ((rc = reset_counters(h))) return rc;
   if (h->prec == DBM_FP64) {
     HIPCHK(hipMemcpy2DAsync(dst, sizeof(double) * ps, f, sizeof(double) * cells,
                             sizeof(double) * cells, nplanes, hipMemcpyHostToDevice, h->stream));
+  } else if (h->om) {
+    // FP64 planes staged in the two spare buffers (each holds S*8 FP64
+    // planes of stride ps), then packed into OM storage.
+    double *lo = (double *)h->inst[inst].buf[(h->cur + 1) % 3];
+    double *hi = (double *)h->inst[inst].buf[(h->cur + 2) % 3];
+    const size_t half = nplanes / 2;
+    HIPCHK(hipMemcpy2DAsync(lo, sizeof(double) * ps, f, sizeof(double) * cells,
+                            sizeof(double) * cells, half, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpy2DAsync(hi, sizeof(double) * ps, f + half * cells, sizeof(double) * cells,
+                            sizeof(double) * cells, nplanes - half, hipMemcpyHostToDevice,
+                            h->stream));
+    HIPCHK(launch_pack_om(h->d_inst(), inst, cells, lo, hi, h->cur, h->stream));
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
@@ -749,6 +925,14 @@ int dbm_get_f(dbm_handle h, int inst, double *f) {
   if (h->prec == DBM_FP64) {
     HIPCHK(hipMemcpy2DAsync(f, sizeof(double) * cells, src, sizeof(double) * ps,
                             sizeof(double) * cells, nplanes, hipMemcpyDeviceToHost, h->stream));
+  } else if (h->om) {
+    double *stage = (double *)h->inst[inst].scratch;
+    for (size_t p = 0; p < nplanes; ++p) {
+      HIPCHK(launch_widen_om(h->d_inst(), inst, cells, h->cur, (int)(p / kNV), (int)(p % kNV),
+                             stage, h->stream));
+      HIPCHK(hipMemcpyAsync(f + p * cells, stage, sizeof(double) * cells, hipMemcpyDeviceToHost,
+                            h->stream));
+    }
   } else {
     double *stage = (double *)h->inst[inst].scratch;
     for (size_t p = 0; p < nplanes; ++p) {
@@ -923,10 +1107,14 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       h->rows = 0;
       h->tiles.clear();
       break;
+    case DBM_OPT_STORAGE:
+      if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "storage must be 0 or 1");
+      h->om_opt = value;
+      break;
     default: return fail(DBM_ERR_ARG, "unknown or read-only option");
   }
   clear_graphs(h);
-  return DBM_OK;
+  return sync_storage(h);
 }
 
 int dbm_get_option(dbm_handle h, int option, int *value) {
@@ -942,16 +1130,18 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
     case DBM_OPT_PIPELINE: *value = h->pipe ? 2 : 1; break;
     case DBM_OPT_ROUNDING: *value = h->sr; break;
+    case DBM_OPT_STORAGE: *value = h->om ? 0 : 1; break;
     case DBM_OPT_CHAIN_WAVE: *value = h->cw ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;
 }
 
-int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
+int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int words, int reps,
                   void *hip_stream, double *ms_per_copy) {
   if (!src || !dst || !ms_per_copy || reps < 1 || grid < 1 || bytes < 16 || bytes % 16 ||
-      ((uintptr_t)src | (uintptr_t)dst) % 16)
+      ((uintptr_t)src | (uintptr_t)dst) % 16 ||
+      !(words == 1 || words == 2 || words == 4 || words == 8))
     return fail(DBM_ERR_ARG, "dbm_copy_rate: bad arguments");
   const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
   if (a < b + bytes && b < a + bytes) return fail(DBM_ERR_ARG, "dbm_copy_rate: buffers overlap");
@@ -959,9 +1149,10 @@ int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   hipError_t e = hipEventCreate(&e1);
-  if (e == hipSuccess) e = launch_copy16(src, dst, bytes / 16, grid, st);  // warm-up
+  if (e == hipSuccess) e = launch_copy16(src, dst, bytes / 16, grid, words, st);  // warm-up
   if (e == hipSuccess) e = hipEventRecord(e0, st);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_copy16(src, dst, bytes / 16, grid, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_copy16(src, dst, bytes / 16, grid, words, st);
   if (e == hipSuccess) e = hipEventRecord(e1, st);
   if (e == hipSuccess) e = hipEventSynchronize(e1);
   float ms = 0.f;
@@ -970,6 +1161,54 @@ int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int reps,
   if (e1) hipEventDestroy(e1);
   if (e != hipSuccess) return fail(DBM_ERR_HIP, std::string("dbm_copy_rate: ") + hipGetErrorString(e));
   *ms_per_copy = ms / reps;
+  return DBM_OK;
+}
+
+size_t dbm_state_bytes(dbm_handle h, int inst) {
+  if (check_inst(h, inst)) return 0;
+  return sizeof(StateHeader) + buffer_bytes(h, inst);
+}
+
+int dbm_save_state(dbm_handle h, int inst, void *dst, size_t bytes) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!dst || bytes < dbm_state_bytes(h, inst)) return fail(DBM_ERR_ARG, "state buffer too small");
+  StateHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  hd.magic = kStateMagic;
+  hd.prec = h->prec;
+  hd.om = h->om ? 1 : 0;
+  hd.S = h->S;
+  hd.nx = h->cfg[inst].nx;
+  hd.ny = h->cfg[inst].ny;
+  hd.sr = h->sr;
+  hd.buffer_bytes = buffer_bytes(h, inst);
+  for (int s = 0; s < h->S; ++s) hd.ref_n[s] = h->ref_n[inst][s];
+  hd.ref_T = h->ref_T[inst];
+  HIPCHK(hipMemcpyAsync(hd.ctr, h->d_ctr(false), sizeof(hd.ctr), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipMemcpyAsync((char *)dst + sizeof(StateHeader), h->inst[inst].buf[h->cur],
+                        hd.buffer_bytes, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  std::memcpy(dst, &hd, sizeof(hd));
+  return DBM_OK;
+}
+
+int dbm_load_state(dbm_handle h, int inst, const void *src, size_t bytes) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!src || bytes < sizeof(StateHeader)) return fail(DBM_ERR_ARG, "state buffer too small");
+  StateHeader hd;
+  std::memcpy(&hd, src, sizeof(hd));
+  if (hd.magic != kStateMagic || hd.prec != h->prec || hd.om != (h->om ? 1 : 0) || hd.S != h->S ||
+      hd.nx != h->cfg[inst].nx || hd.ny != h->cfg[inst].ny ||
+      hd.buffer_bytes != buffer_bytes(h, inst) || bytes < dbm_state_bytes(h, inst))
+    return fail(DBM_ERR_ARG, "state blob does not match this handle's configuration");
+  std::vector<double> nm(hd.ref_n, hd.ref_n + h->S);
+  if ((rc = set_om_reference(h, inst, nm, hd.ref_T))) return rc;
+  HIPCHK(hipMemcpyAsync(h->inst[inst].buf[h->cur], (const char *)src + sizeof(StateHeader),
+                        hd.buffer_bytes, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->d_ctr(false), hd.ctr, sizeof(hd.ctr), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
   return DBM_OK;
 }
 

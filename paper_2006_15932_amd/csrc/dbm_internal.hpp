@@ -51,7 +51,21 @@ struct SpeciesDev {
   float MA_f[16], MB1_f[4], MB2_f[4], ME_f[16];
   float vg_f[4], qg_f[4];
   int mirx[kNV], miry[kNV];
-  int pad_[2];
+  // Shifted orbit-moment storage of FP32-bulk f (OM storage).  Per cell and
+  // species the 16 stored values are
+  //   s[0..3]   the A-block moments (rows 1, v^2+eta^2, v_x^2+v_y^2,
+  //             (v^2+eta^2)(v_x^2+v_y^2)) of f - fref: n - n_ref, E - E_ref, ...
+  //   s[4..7]   B_a, B_b, B_c, B_d   (orbit alternating sums of f)
+  //   s[8..11]  X_a .. X_d           (orbit sums signed by v_x)
+  //   s[12..15] Y_a .. Y_d           (orbit sums signed by v_y)
+  // with fref = f^eq(n_ref, 0, T_ref) a fixed equilibrium at rest, whose B, X
+  // and Y vanish.  iA, iB1, iB2, iE are the plain inverses of the blocks
+  // (moments -> orbit components); the FP32 copies of iB and iE carry the
+  // factor omega = dt/tau of the collision.
+  double fref[kNV];      // reference distribution f^eq(n_ref, 0, T_ref)
+  double sref[4];        // its A-block moments
+  double iA[16], iB1[4], iB2[4], iE[16];
+  float wB1_f[4], wB2_f[4], wE_f[16];
 };
 
 // Elements from one plane of an f buffer to the next: the nx*ny cells plus
@@ -85,7 +99,7 @@ struct InstDev {
   double ax, ay;
   double dt, dx, dy;
   int lim;
-  int pad_;
+  int om;                // FP32-bulk buffers hold OM storage (see SpeciesDev)
 };
 
 // One tile: a wavefront marches `rows` rows of 64 columns starting at (x0, y0).

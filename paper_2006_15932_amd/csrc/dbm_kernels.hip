@@ -240,6 +240,9 @@ __device__ __forceinline__ double join_f32x(float hi, uint16_t lo) {
 // The random bits are a hash of the cell, the species and the values being
 // updated (the state itself): results stay deterministic and do not depend on
 // tiling or launch order.
+// mix32 is the 32-bit integer finaliser "lowbias32" published by C. Wellons
+// (hash-prospector, 2018): xor-shift 16, multiply, xor-shift 15, multiply,
+// xor-shift 16, with the two multipliers found there by search.
 __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -260,6 +263,33 @@ __device__ __forceinline__ float sr_add(float f, float d, uint32_t u8) {
   const float E = __uint_as_float(__float_as_uint(sm) & 0x7f800000u);
   const float t = fma((float)(u8 & 0xffu), 0x1p-31f, 0x1p-32f - 0x1p-24f);
   return sm + fma(E, t, er);
+}
+
+// Step counter of stochastic rounding: ctr[0] is read by every workgroup at
+// the start of a launch; the last workgroup to finish advances it (ctr[1]
+// counts the finished workgroups), so each launch draws new random bits.
+__device__ __forceinline__ void advance_step_counter(uint32_t *ctr, uint32_t step,
+                                                     uint32_t nblocks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const uint32_t done = atomicAdd(&ctr[1], 1u);
+    if (done == nblocks - 1) {
+      __threadfence();
+      __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr[0], step + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// The 32-bit key of a row's stochastic roundings: cell, species, launch and
+// the values being updated, combined with the golden-ratio multiplier
+// 0x9E3779B9 and the odd constants of MurmurHash3's finaliser and xxHash.
+__device__ __forceinline__ uint32_t sr_key(uint32_t cell, int s, uint32_t step, const float *v) {
+  uint32_t key = cell * 0x9E3779B9u ^ (uint32_t)(s + 1) * 0x85EBCA6Bu ^ step * 0xC2B2AE35u;
+#pragma unroll
+  for (int i = 0; i < kNV; ++i) key = (key ^ __float_as_uint(v[i])) + (uint32_t)i * 0x27D4EB2Fu;
+  return key;
 }
 
 // Element access to one buffer of n values (generic kernels).
@@ -823,7 +853,7 @@ template <typename T> constexpr bool kHaloGather = sizeof(T) == 4 ? DBM_GATHER_F
 template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR, bool CW>
 __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0, int y0,
                                            int rows, int in_idx, int fn_idx, int out_idx,
-                                           typename Stor<ST>::C alpha,
+                                           typename Stor<ST>::C alpha, uint32_t step,
                                            double (*mom)[4 * S][kWave],
                                            double (*chn)[kChainRows<S, CW>][kWave]) {
   typedef typename Stor<ST>::C T;                  // arithmetic type
@@ -1076,13 +1106,11 @@ __device__ __forceinline__ void fused_tile(const InstDev &I, const int s, int x0
     T res[kNV];
     // Stochastic rounding: the increment d is formed apart from f and the
     // sum rounded once, with 8 random bits per value from four independent
-    // hashes per lane and row of one key (each key step one xor-add).
+    // hashes per lane and row of one key (cell, species, launch, state).
     constexpr bool kSR = SR && std::is_same<ST, float>::value;
     uint32_t rb[4];
     if constexpr (kSR) {
-      uint32_t key = (uint32_t)(rk + col) * 0x9E3779B9u ^ (uint32_t)(s + 1) * 0x85EBCA6Bu;
-#pragma unroll
-      for (int i = 0; i < kNV; ++i) key = (key ^ __float_as_uint(c[i])) + (uint32_t)i * 0x27D4EB2Fu;
+      const uint32_t key = sr_key((uint32_t)(rk + col), s, step, c);
       rb[0] = mix32(key);
       rb[1] = mix32(key ^ 0x68E31DA4u);
       rb[2] = mix32(key ^ 0xB5297A4Du);
@@ -1486,20 +1514,24 @@ __device__ __forceinline__ void chain_tile(const InstDev &I, int y0, int rows,
 template <typename ST, int S, int LIM, bool RKC, bool PIPE, bool SR, bool CW>
 __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), Occ<ST>::kMinWaves) void k_fused_stage(
     const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
-    int fn_idx, int out_idx, typename Stor<ST>::C alpha, int remap) {
+    int fn_idx, int out_idx, typename Stor<ST>::C alpha, int remap, uint32_t *ctr) {
   __shared__ double mom[2][4 * S][kWave];
   __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  constexpr bool kSR = SR && std::is_same<ST, float>::value;
+  uint32_t step = 0;
+  if constexpr (kSR) step = __hip_atomic_load(&ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
     if (CW && s == S) {
       if constexpr (CW) chain_tile<typename Stor<ST>::C, S>(insts[t.inst], t.y0, t.rows, mom, chn);
     } else {
       fused_tile<ST, S, LIM, RKC, PIPE, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx,
-                                                fn_idx, out_idx, alpha, mom, chn);
+                                                fn_idx, out_idx, alpha, step, mom, chn);
     }
     __syncthreads();
   }
+  if constexpr (kSR) advance_step_counter(ctr, step, gridDim.x);
 }
 
 #ifndef DBM_MIN_WAVES_SPLIT_F32
@@ -1531,6 +1563,618 @@ __global__ __launch_bounds__(kWave * 2 * S, OccSplit<T>::kMinWaves) void k_fused
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// OM storage of FP32-bulk f (see SpeciesDev): per cell and species the
+// A-block moments of f - fref and the orbit components B, X, Y of f.
+//
+// Storing f_i itself in FP32 rounds each value to 2^-24 of its size, so the
+// momentum sum_i f_i v_i and the mass and energy carry rounding noise of
+// order 2^-24 |f| c per step whatever the flow speed is.  Stored this way,
+// the mass and energy are kept as differences from a fixed reference state
+// and the momentum as the signed orbit sums X, Y, each rounded relative to its
+// own size: near rest and near the reference the noise shrinks with the
+// deviation.  The representation is a fixed invertible linear map of f, so
+// each update is formed as an increment in the same basis (from the
+// convection of the reconstructed f - fref and the moment-space collision)
+// and added to the stored values with one rounding.
+// ---------------------------------------------------------------------------
+
+// Slot pattern of a specular reflection in y (v_y -> -v_y): the diagonal
+// groups' B and every Y change sign, the rest is invariant.
+__host__ __device__ constexpr bool om_odd_in_y(int k) {
+  return k == 5 || k == 7 || k >= 12;
+}
+__device__ __forceinline__ void om_flip(float *s, bool flip) {
+  if (flip) {
+#pragma unroll
+    for (int k = 0; k < kNV; ++k)
+      if (om_odd_in_y(k)) s[k] = -s[k];
+  }
+}
+
+// f - fref (plane order of Eq.15) from the stored values, FP32 arithmetic:
+// a_g = A_g / 4 from the A-block moments, then each group from a, B, X, Y.
+__device__ __forceinline__ void om_recon(SpC &sp, const float *s, float *f) {
+  const float DBM_CONST *KA = sp.KA_f;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float al = KA[g * 4] * s[0];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) al = fma(KA[g * 4 + j], s[j], al);
+    const float B = s[4 + g], X = s[8 + g], Y = s[12 + g];
+    const float p = fma(0.25f, B, al), m = fma(-0.25f, B, al);
+    float *o = f + 4 * g;
+    if ((g & 1) == 0) {
+      o[0] = fma(0.5f, X, p); o[1] = fma(0.5f, Y, m);
+      o[2] = fma(-0.5f, X, p); o[3] = fma(-0.5f, Y, m);
+    } else {
+      const float sm = X + Y, df = X - Y;
+      o[0] = fma(0.25f, sm, p); o[1] = fma(-0.25f, df, m);
+      o[2] = fma(-0.25f, sm, p); o[3] = fma(0.25f, df, m);
+    }
+  }
+}
+
+// Increment of the stored values for an increment dc of f (plane order):
+// orbit components of dc, and the A-block moments of its orbit sums.
+__device__ __forceinline__ void om_project(SpC &sp, const float *dc, float *ds) {
+  float A[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const float c0 = dc[4 * g], c1 = dc[4 * g + 1], c2 = dc[4 * g + 2], c3 = dc[4 * g + 3];
+    const float s02 = c0 + c2, s13 = c1 + c3;
+    A[g] = s02 + s13;
+    ds[4 + g] = s02 - s13;
+    if ((g & 1) == 0) {
+      ds[8 + g] = c0 - c2; ds[12 + g] = c1 - c3;
+    } else {
+      ds[8 + g] = (c0 + c3) - (c1 + c2); ds[12 + g] = (c0 + c1) - (c2 + c3);
+    }
+  }
+  const float DBM_CONST *MA = sp.MA_f;
+  ds[0] = (A[0] + A[1]) + (A[2] + A[3]);
+#pragma unroll
+  for (int j = 1; j < 4; ++j) {
+    float m = MA[j * 4] * A[0];
+#pragma unroll
+    for (int g = 1; g < 4; ++g) m = fma(MA[j * 4 + g], A[g], m);
+    ds[j] = m;
+  }
+}
+
+// Adds the collision increment omega M^{-1} d, expressed in the stored basis,
+// to ds: omega d for the A-block moments, omega (iB, iE) d for B, X, Y.
+__device__ __forceinline__ void om_add_collision(SpC &sp, const float *d, float *ds) {
+  const float om = sp.omega_f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) ds[j] = fma(om, d[j], ds[j]);
+  const float DBM_CONST *B1 = sp.wB1_f;
+  const float DBM_CONST *B2 = sp.wB2_f;
+  ds[4] = fma(B1[1], d[5], fma(B1[0], d[4], ds[4]));
+  ds[6] = fma(B1[3], d[5], fma(B1[2], d[4], ds[6]));
+  ds[5] = fma(B2[1], d[7], fma(B2[0], d[6], ds[5]));
+  ds[7] = fma(B2[3], d[7], fma(B2[2], d[6], ds[7]));
+  const float DBM_CONST *E = sp.wE_f;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    float x = ds[8 + g], y = ds[12 + g];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      x = fma(E[g * 4 + j], d[8 + j], x);
+      y = fma(E[g * 4 + j], d[12 + j], y);
+    }
+    ds[8 + g] = x;
+    ds[12 + g] = y;
+  }
+}
+
+// FP64 species moments from the stored values: n and E are the first two
+// A-block moments plus the reference's, j = sum_g v_g (X_g, Y_g).
+__device__ __forceinline__ void om_moments(SpC &sp, const float *s, double &n, double &jx,
+                                           double &jy, double &E) {
+  n = (double)s[0] + sp.sref[0];
+  E = (double)s[1] + sp.sref[1];
+  jx = jy = 0.0;
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    jx = fma(sp.vg[g], (double)s[8 + g], jx);
+    jy = fma(sp.vg[g], (double)s[12 + g], jy);
+  }
+}
+
+// g - M f of one species in the order of eq_rhs (collision_rhs on OM
+// storage): the conserved rows 0, 1, 8, 12 and the A-block rows 2, 3 are
+// differenced in FP64 against the stored moments plus the reference's; the
+// B, X and Y rows in FP32, where both terms are small near rest.
+__device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, const float *s,
+                                                 double n, double jx, double jy, double E,
+                                                 double ns, double ux, double uy, double Tst,
+                                                 float *d) {
+  const double K = sp.K, th = Tst * sp.inv_m, u2 = ux * ux + uy * uy;
+  float r[16];
+  eq_rhs<float>((float)ns, (float)ux, (float)uy, (float)th, (float)K, r);
+  const double e2 = (K + 2.0) * th + u2, e4 = (K + 4.0) * th + u2;
+  double d0 = ns - n, d1 = ns * fma(K, th, u2) - E, d8 = ns * ux - jx, d12 = ns * uy - jy;
+  double d2 = (ns * (2.0 * th + u2) - sp.sref[2]) - (double)s[2];
+  double d3 = (ns * fma(2.0 * th, e2, u2 * e4) - sp.sref[3]) - (double)s[3];
+  const bool force = I.force && n > 1e-300;
+  double fd[16];
+  if (force) {
+    const double inv_n = recip<float>(n);
+    const double us = jx * inv_n, vs = jy * inv_n;
+    const double Ts = sp.m * (E * inv_n - us * us - vs * vs) * sp.inv_K;
+    double Td = Ts;
+    if (I.fmode == DBM_FORCE_T_EXACT)
+      Td = Ts - sp.m * sp.tau * sp.tau * (I.ax * I.ax + I.ay * I.ay) * sp.inv_K;
+    double r1[16], r2[16];
+    eq_rhs<double>(n, us + sp.tau * I.ax, vs + sp.tau * I.ay, Td * sp.inv_m, K, r1);
+    eq_rhs<double>(n, us, vs, Ts * sp.inv_m, K, r2);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) fd[k] = r1[k] - r2[k];
+    d0 += fd[0];
+    d1 += fd[1];
+    d2 += fd[2];
+    d3 += fd[3];
+    d8 += fd[8];
+    d12 += fd[12];
+  }
+  const float DBM_CONST *MB1 = launder_after(sp.MB1_f, r[4]);
+  const float DBM_CONST *MB2 = launder_after(sp.MB2_f, r[6]);
+  const float DBM_CONST *ME = launder_after(sp.ME_f, r[9]);
+  d[0] = (float)d0;
+  d[1] = (float)d1;
+  d[2] = (float)d2;
+  d[3] = (float)d3;
+  d[8] = (float)d8;
+  d[12] = (float)d12;
+  d[4] = r[4] - fma(MB1[1], s[6], MB1[0] * s[4]);
+  d[5] = r[5] - fma(MB1[3], s[6], MB1[2] * s[4]);
+  d[6] = r[6] - fma(MB2[1], s[7], MB2[0] * s[5]);
+  d[7] = r[7] - fma(MB2[3], s[7], MB2[2] * s[5]);
+#pragma unroll
+  for (int row = 1; row < 4; ++row) {
+    float mx = ME[row * 4] * s[8], my = ME[row * 4] * s[12];
+#pragma unroll
+    for (int j = 1; j < 4; ++j) {
+      mx = fma(ME[row * 4 + j], s[8 + j], mx);
+      my = fma(ME[row * 4 + j], s[12 + j], my);
+    }
+    d[8 + row] = r[8 + row] - mx;
+    d[12 + row] = r[12 + row] - my;
+  }
+  if (force) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+      if (k != 0 && k != 1 && k != 2 && k != 3 && k != 8 && k != 12) d[k] += (float)fd[k];
+  }
+}
+
+// FP64 conversions between f and OM storage (initialisation, transfers,
+// diagnostics and changes of representation).
+__device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *f, float *s) {
+  double A[4];
+  for (int g = 0; g < 4; ++g) {
+    const double c0 = f[4 * g] - sp.fref[4 * g], c1 = f[4 * g + 1] - sp.fref[4 * g + 1];
+    const double c2 = f[4 * g + 2] - sp.fref[4 * g + 2], c3 = f[4 * g + 3] - sp.fref[4 * g + 3];
+    A[g] = (c0 + c2) + (c1 + c3);
+    s[4 + g] = (float)((c0 + c2) - (c1 + c3));
+    if ((g & 1) == 0) {
+      s[8 + g] = (float)(c0 - c2);
+      s[12 + g] = (float)(c1 - c3);
+    } else {
+      s[8 + g] = (float)((c0 + c3) - (c1 + c2));
+      s[12 + g] = (float)((c0 + c1) - (c2 + c3));
+    }
+  }
+  for (int j = 0; j < 4; ++j) {
+    double m = 0.0;
+    for (int g = 0; g < 4; ++g) m = fma(sp.MA[j * 4 + g], A[g], m);
+    s[j] = (float)m;
+  }
+}
+__device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const float *s, double *f) {
+  for (int g = 0; g < 4; ++g) {
+    double A = 0.0;
+    for (int j = 0; j < 4; ++j) A = fma(sp.iA[g * 4 + j], (double)s[j], A);
+    const double B = s[4 + g], X = s[8 + g], Y = s[12 + g];
+    const double p = 0.25 * (A + B), m = 0.25 * (A - B);
+    double *o = f + 4 * g;
+    if ((g & 1) == 0) {
+      o[0] = p + 0.5 * X; o[1] = m + 0.5 * Y; o[2] = p - 0.5 * X; o[3] = m - 0.5 * Y;
+    } else {
+      const double sm = 0.25 * (X + Y), df = 0.25 * (X - Y);
+      o[0] = p + sm; o[1] = m - df; o[2] = p - sm; o[3] = m + df;
+    }
+    for (int k = 0; k < 4; ++k) o[k] += sp.fref[4 * g + k];
+  }
+}
+
+// DPP broadcasts used by the halo transform: row_newbcast:n gives every lane
+// of a 16-lane row the value of lane n of that row; quad_perm [q,q,q,q] the
+// value of lane q of its quad.
+template <int N> __device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + N, 0xf, 0xf, false));
+}
+template <int Q> __device__ __forceinline__ float quad_bcast(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_mov_dpp(__float_as_int(v), Q | (Q << 2) | (Q << 4) | (Q << 6), 0xf, 0xf, false));
+}
+
+// Rows of loads in flight per wavefront (OM form).
+#ifndef DBM_OM_RING
+#define DBM_OM_RING 2
+#endif
+constexpr int kRingOM = DBM_OM_RING;
+static_assert(kRingOM >= 2, "the prefetch ring needs two or more slots");
+
+// The per-wavefront hold of stored rows: row r's 16 stored values sit in
+// slot r % 3 from the time they are loaded (two rows ahead, for the
+// stencil's look-ahead) until row r's own update, as four float4 per lane.
+typedef float float4_t __attribute__((ext_vector_type(4)));
+constexpr int kHoldRows = 3;
+
+// One wavefront's share of a tile on OM storage (FP32-bulk): species `s`,
+// 64 lanes = columns x0 .. x0+63, rows y0 .. y0+rows-1, marching in +y.
+//  * Stored row r arrives two rows ahead (the look-ahead of planes with
+//    v_y < 0), is reconstructed to f - fref once (the planes with v_y >= 0
+//    keep it for one more row) and parked in the hold until row r is updated.
+//  * The x-halo (columns x0-2, x0-1, x0+64, x0+65) arrives as one load of
+//    all 16 stored values of those four cells (lane 16 w + 4 g + q: column w,
+//    slot 4 q + g) and is turned into f - fref by two rounds of DPP
+//    broadcasts: the A-block moments into a_g within each 16-lane row, then
+//    a, B, X, Y into the group's four planes within each quad (lane 16 w + i:
+//    plane i at column w).  The edge lanes then gather it as in fused_tile.
+//  * The update of row k is formed in the stored basis: the stencil
+//    increment projected onto it plus the moment-space collision, added to
+//    row k's stored values with one rounding.
+template <int S, int LIM, bool RKC, bool SR, bool CW>
+__device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int x0, int y0,
+                                              int rows, int in_idx, int fn_idx, int out_idx,
+                                              float alpha, uint32_t step,
+                                              double (*mom)[4 * S][kWave],
+                                              double (*chn)[kChainRows<S, CW>][kWave],
+                                              float4_t (*hold)[4][kWave]) {
+  typedef float T;
+  constexpr int kPf = kRingOM;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nx = I.nx, ny = I.ny, bcy = I.bcy;
+  const FBuf<float> bin(I, in_idx, s), bfn(I, fn_idx, s), bout(I, out_idx, s);
+  const int col = x0 + lane;
+  const int lcol = map_x(col, nx, I.bcx);
+  const bool writer = col < nx;
+  const int yend = y0 + rows;
+
+  auto hold_put = [&](int r, const T *v) {
+    float4_t(*h)[kWave] = hold[r % kHoldRows];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) h[q][lane] = float4_t{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
+  };
+  auto hold_get = [&](int r, T *v) {
+    float4_t(*h)[kWave] = hold[r % kHoldRows];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float4_t w = h[q][lane];
+      v[4 * q] = w.x; v[4 * q + 1] = w.y; v[4 * q + 2] = w.z; v[4 * q + 3] = w.w;
+    }
+  };
+  // Stored row r at this lane's column (reflected rows: see om_flip).
+  auto load_row = [&](int r, T *dst, bool &flip) {
+    const int rr = map_y(r, ny, bcy, flip) * nx;
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) dst[i] = bin.value((uint32_t)(rr + lcol), i);
+  };
+
+  // Halo lanes: lane 16 w + 4 g + q reads slot 4 q + g of column w.
+  const int hw = lane >> 4, hg = (lane >> 2) & 3, hq = lane & 3;
+  const uint32_t hplane = (uint32_t)(4 * hq + hg);
+  uint32_t hcol;
+  {
+    const int c = hw == 0 ? x0 - 2 : (hw == 1 ? x0 - 1 : (hw == 2 ? x0 + kWave : x0 + kWave + 1));
+    hcol = (uint32_t)map_x(c, nx, I.bcx);
+  }
+  // Transform coefficients.  Round 1 (A-block moments -> a_g, in the lanes
+  // with q = 0; the others keep their value): a = own * hown + sum_j hcA[j] *
+  // (slot j of the row).  Round 2 (plane 4 g + c from a_g, B_g, X_g, Y_g):
+  // coefficients 1, hcB, hcX, hcY.
+  T hown, hcA[4], hcB, hcX, hcY;
+  {
+    SpC &me = launder(as_const(I.sp))[s];
+    hown = hq == 0 ? 0.f : 1.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T k0 = me.KA_f[j], k1 = me.KA_f[4 + j], k2 = me.KA_f[8 + j], k3 = me.KA_f[12 + j];
+      const T kg = hg == 0 ? k0 : (hg == 1 ? k1 : (hg == 2 ? k2 : k3));
+      hcA[j] = hq == 0 ? kg : 0.f;
+    }
+    const int c = hq;
+    hcB = (c & 1) ? -0.25f : 0.25f;
+    if ((hg & 1) == 0) {          // axis group: planes +x, +y, -x, -y
+      hcX = c == 0 ? 0.5f : (c == 2 ? -0.5f : 0.f);
+      hcY = c == 1 ? 0.5f : (c == 3 ? -0.5f : 0.f);
+    } else {                      // diagonal group: (1,1), (-1,1), (-1,-1), (1,-1)
+      hcX = (c == 0 || c == 3) ? 0.25f : -0.25f;
+      hcY = (c == 0 || c == 1) ? 0.25f : -0.25f;
+    }
+  }
+  const int hidx1 = lane == kWave - 1 ? 32 * 4 : 16 * 4;
+
+  // Rows y0-2 .. y0+1: the stencil state of row y0 and the first two rows
+  // of the hold.
+  T c[kNV], y1[kNV], y2[kNV], nxv[kNV];
+  {
+    SpC &me = launder(as_const(I.sp))[s];
+    T sa[kNV], sb[kNV], s0[kNV], s1[kNV];
+    bool fa, fb, f0, f1;
+    load_row(y0 - 2, sa, fa);
+    load_row(y0 - 1, sb, fb);
+    load_row(y0, s0, f0);
+    load_row(y0 + 1, s1, f1);
+    om_flip(sa, fa);
+    om_flip(sb, fb);
+    om_flip(s1, f1);
+    hold_put(y0, s0);
+    if (y0 + 1 < yend) hold_put(y0 + 1, s1);
+    T ra[kNV], rb[kNV], r1[kNV];
+    om_recon(me, sa, ra);
+    om_recon(me, sb, rb);
+    om_recon(me, s0, c);
+    om_recon(me, s1, r1);
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) {
+      const int sy = plane_sy(i);
+      if (sy > 0) {
+        y1[i] = c[i] - rb[i];
+        y2[i] = slope_pos<LIM>(rb[i] - ra[i], c[i] - rb[i]);
+        nxv[i] = r1[i];
+      } else if (sy < 0) {
+        y1[i] = r1[i];
+        y2[i] = slope_neg<LIM>(c[i] - rb[i], r1[i] - c[i]);
+        nxv[i] = T(0);
+      } else {
+        y1[i] = y2[i] = T(0);
+        nxv[i] = r1[i];
+      }
+    }
+    if constexpr (CW) {   // row y0's moments for the chain wavefront's first chain
+      double n0, jx0, jy0, E0;
+      om_moments(me, s0, n0, jx0, jy0, E0);
+      double(*mb)[kWave] = mom[y0 & 1];
+      mb[0 * S + s][lane] = n0;
+      mb[1 * S + s][lane] = jx0;
+      mb[2 * S + s][lane] = jy0;
+      mb[3 * S + s][lane] = E0;
+      __syncthreads();
+    }
+  }
+
+  // Ring slot of time t: stored row t+2 (with its reflection flag) and the
+  // raw halo of row t.
+  auto issue = [&](int t, T *dst, T &halo, bool &flip) {
+    load_row(t + 2, dst, flip);
+    halo = bin.lane_value(hplane, hcol + (uint32_t)(t * nx));
+  };
+  T ring[kPf][kNV];
+  T hring[kPf];
+  bool rflip[kPf];
+#pragma unroll
+  for (int d = 0; d < kPf - 1; ++d)
+    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d], rflip[d]);
+
+  auto row = [&](int k, const T *cur, const T hcur, const bool cflip, T *refill, T &hrefill,
+                 bool &rfl) {
+    if (k + kPf - 1 < yend) issue(k + kPf - 1, refill, hrefill, rfl);
+    const int rk = k * nx;
+    SpC *sp = launder(as_const(I.sp));
+    SpC &me = sp[s];
+    // Stored row k+2: hold it for its own update, reconstruct it for the
+    // stencil (planes with v_y < 0 now, the others next row).
+    T fnew[kNV];
+    {
+      T sn[kNV];
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) sn[i] = cur[i];
+      om_flip(sn, cflip);
+      if (k + 2 < yend) hold_put(k + 2, sn);
+      om_recon(me, sn, fnew);
+    }
+    T nv[kNV];
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) {
+      if (plane_sy(i) < 0) {
+        nv[i] = fnew[i];
+      } else {
+        nv[i] = nxv[i];
+        nxv[i] = fnew[i];
+      }
+    }
+    // x-halo of row k as f - fref, and its gathers to the edge lanes.
+    T hf;
+    {
+      T a = hown * hcur;
+      a = fma(hcA[0], row_bcast<0>(hcur), a);
+      a = fma(hcA[1], row_bcast<4>(hcur), a);
+      a = fma(hcA[2], row_bcast<8>(hcur), a);
+      a = fma(hcA[3], row_bcast<12>(hcur), a);
+      hf = quad_bcast<0>(a);
+      hf = fma(hcB, quad_bcast<1>(a), hf);
+      hf = fma(hcX, quad_bcast<2>(a), hf);
+      hf = fma(hcY, quad_bcast<3>(a), hf);
+    }
+    T h1[kXPlanes], h2[kXPlanes];
+#pragma unroll
+    for (int j = 0; j < kXPlanes; ++j) {
+      const int i = xplane(j);
+      h1[j] = bperm(hidx1 + 4 * i, hf);
+      h2[j] = bperm(4 * (plane_sx(i) > 0 ? i : 48 + i), hf);
+    }
+    T cgx[4], cgy[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      cgx[g] = me.cgx_f[g];
+      cgy[g] = me.cgy_f[g];
+    }
+    // Stencil increments of row k (NND in x from adjacent lanes and the
+    // halo, in y from the carried rows); advances the carried state.
+    T dc[kNV];
+#pragma unroll
+    for (int i = 0; i < kNV; ++i) {
+      const int g = i >> 2, sx = plane_sx(i), sy = plane_sy(i);
+      const T f = c[i];
+      T a = T(0);
+      if (sx != 0) {
+        const int j = xplane_index(i);
+        const T dl = f - h1[j];
+        const T e = sx > 0 ? h1[j] - h2[j] : h2[j] - h1[j];
+        const T dp = shl1e(f, h1[j]) - f;
+        T Dx;
+        if (sx > 0) {
+          const T sle = slope_pos<LIM>(e, dl);
+          const T d0 = shr1e(dp, dl);
+          const T sl = slope_pos<LIM>(d0, dp);
+          Dx = fma(T(0.5), sl - shr1e(sl, sle), d0);
+          a = -cgx[g] * Dx;
+        } else {
+          const T sle = slope_neg<LIM>(dl, dp);
+          const T dhi = shl1e(dp, e);
+          const T sl = slope_neg<LIM>(dp, dhi);
+          Dx = fma(T(-0.5), sl - shr1e(sl, sle), dp);
+          a = cgx[g] * Dx;
+        }
+      }
+      const T fn = nv[i];
+      if (sy > 0) {
+        const T dn = fn - f;
+        const T sk = slope_pos<LIM>(y1[i], dn);
+        const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
+        a = fma(-cgy[g], Dy, a);
+        c[i] = fn;
+        y1[i] = dn;
+        y2[i] = sk;
+      } else if (sy < 0) {
+        const T n1 = y1[i];
+        const T dlo = n1 - f, dhi = fn - n1;
+        const T tk1 = slope_neg<LIM>(dlo, dhi);
+        const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
+        a = fma(cgy[g], Dy, a);
+        c[i] = n1;
+        y1[i] = fn;
+        y2[i] = tk1;
+      } else {
+        c[i] = fn;
+      }
+      dc[i] = a;
+    }
+    // Collision of row k from its stored values.
+    T sk[kNV];
+    hold_get(k, sk);
+    double n0, jx0, jy0, E0;
+    om_moments(me, sk, n0, jx0, jy0, E0);
+    double ux, uy, Tst, dn;
+    if constexpr (CW) {
+      if (k + 1 < yend) {   // row k+1's moments for the chain wavefront
+        T s1[kNV];
+        hold_get(k + 1, s1);
+        double n1, jx1, jy1, E1;
+        om_moments(me, s1, n1, jx1, jy1, E1);
+        double(*mb)[kWave] = mom[(k + 1) & 1];
+        mb[0 * S + s][lane] = n1;
+        mb[1 * S + s][lane] = jx1;
+        mb[2 * S + s][lane] = jy1;
+        mb[3 * S + s][lane] = E1;
+      }
+      __syncthreads();
+      double(*cb)[kWave] = chn[k & 1];
+      ux = cb[0][lane];
+      uy = cb[1][lane];
+      Tst = cb[2][lane];
+      dn = cb[3 + s][lane];
+    } else {
+      double(*mb)[kWave] = mom[k & 1];
+      mb[0 * S + s][lane] = n0;
+      mb[1 * S + s][lane] = jx0;
+      mb[2 * S + s][lane] = jy0;
+      mb[3 * S + s][lane] = E0;
+      __syncthreads();
+      CellState cs;
+      cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
+      dn = cs.dn[0];
+#pragma unroll
+      for (int q = 1; q < S; ++q)
+        if (q == s) dn = cs.dn[q];   // wave-uniform select, no indexed array
+      ux = cs.ux;
+      uy = cs.uy;
+      Tst = cs.Tst;
+    }
+    T d[kNV];
+    collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
+    T ds[kNV];
+    om_project(me, dc, ds);
+    om_add_collision(me, d, ds);
+    // Stage combine in the stored basis and one store per value.
+    T res[kNV];
+    const int rkn = k < ny ? rk : (ny - 1) * nx;
+    if constexpr (SR) {
+      const uint32_t key = sr_key((uint32_t)(rk + col), s, step, sk);
+      uint32_t rb[4];
+      rb[0] = mix32(key);
+      rb[1] = mix32(key ^ 0x68E31DA4u);
+      rb[2] = mix32(key ^ 0xB5297A4Du);
+      rb[3] = mix32(key ^ 0x1B56C4E9u);
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) {
+        T dd = ds[i];
+        if constexpr (RKC) dd = fma(alpha, (bfn.value((uint32_t)(rkn + lcol), i) - sk[i]) - dd, dd);
+        res[i] = sr_add(sk[i], dd, rb[i >> 2] >> (8 * (i & 3)));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) {
+        res[i] = sk[i] + ds[i];
+        if constexpr (RKC) res[i] = fma(alpha, bfn.value((uint32_t)(rkn + lcol), i) - res[i], res[i]);
+      }
+    }
+    if (writer) {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) bout.store((uint32_t)(rk + col), i, res[i]);
+    }
+  };
+
+  for (int k = y0; k < yend; k += kPf) {
+#pragma unroll
+    for (int d = 0; d < kPf; ++d) {
+      if (k + d < yend)
+        row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+            hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+    }
+  }
+}
+
+// One workgroup = S wavefronts (plus the chain wavefront with CW), tiles
+// taken persistently in XCD-grouped order, as k_fused_stage.
+template <int S, int LIM, bool RKC, bool SR, bool CW>
+__global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void k_fused_om(
+    const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
+    int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr) {
+  __shared__ double mom[2][4 * S][kWave];
+  __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
+  __shared__ float4_t hold[S][kHoldRows][4][kWave];
+  const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  uint32_t step = 0;
+  if constexpr (SR) step = __hip_atomic_load(&ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
+    if (CW && s == S) {
+      if constexpr (CW) chain_tile<float, S>(insts[t.inst], t.y0, t.rows, mom, chn);
+    } else {
+      fused_tile_om<S, LIM, RKC, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
+                                          out_idx, alpha, step, mom, chn,
+                                          hold[CW && s == S ? 0 : s]);
+    }
+    __syncthreads();
+  }
+  if constexpr (SR) advance_step_counter(ctr, step, gridDim.x);
+}
 
 // ---------------------------------------------------------------------------
 // Plain path: one thread per cell for the equilibrium (dense FP64 M^{-1}),
@@ -1672,10 +2316,10 @@ __device__ __forceinline__ T nnd_face(T fm1, T f0, T fp1, T fp2, int sgn, int li
 }
 
 template <typename ST>
-__global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict__ insts,
-                                                      int inst, int in_idx, int fn_idx,
-                                                      int out_idx, typename Stor<ST>::C alpha,
-                                                      int rkc, int sr) {
+__device__ __forceinline__ void plain_update_cell(const InstDev *__restrict__ insts, int inst,
+                                                  int in_idx, int fn_idx, int out_idx,
+                                                  typename Stor<ST>::C alpha, int rkc, bool sr,
+                                                  uint32_t step) {
   typedef typename Stor<ST>::C T;
   const InstDev &I = insts[inst];
   const size_t plane = (size_t)I.nx * I.ny;
@@ -1706,17 +2350,29 @@ __global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict_
   }
   const T feq = ((const T *)I.scratch)[(size_t)si * plane + cell];
   T res;
-  if (std::is_same<ST, float>::value && sr) {   // stochastic rounding (see sr_add)
+  if (sr) {   // stochastic rounding (see sr_add)
     T d = C + (T)sp.omega * (feq - fc);
     if (rkc) d = fma(alpha, (fview<ST>(I, fn_idx)[(size_t)si * I.ps + cell] - fc) - d, d);
     const uint32_t key = (uint32_t)cell * 0x9E3779B9u ^ (uint32_t)(si + 1) * 0x85EBCA6Bu ^
-                         (uint32_t)__float_as_uint((float)fc);
+                         step * 0xC2B2AE35u ^ (uint32_t)__float_as_uint((float)fc);
     res = (T)sr_add((float)fc, (float)d, mix32(key));
   } else {
     res = fc + C + (T)sp.omega * (feq - fc);
     if (rkc) res = fma(alpha, fview<ST>(I, fn_idx)[(size_t)si * I.ps + cell] - res, res);
   }
   fview<ST>(I, out_idx).set((size_t)si * I.ps + cell, res);
+}
+
+template <typename ST>
+__global__ __launch_bounds__(256) void k_plain_update(const InstDev *__restrict__ insts,
+                                                      int inst, int in_idx, int fn_idx,
+                                                      int out_idx, typename Stor<ST>::C alpha,
+                                                      int rkc, int sr, uint32_t *ctr) {
+  const bool kSR = std::is_same<ST, float>::value && sr;
+  uint32_t step = 0;
+  if (kSR) step = __hip_atomic_load(&ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  plain_update_cell<ST>(insts, inst, in_idx, fn_idx, out_idx, alpha, rkc, kSR, step);
+  if (kSR) advance_step_counter(ctr, step, gridDim.x * gridDim.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -1756,12 +2412,36 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
                            nn * (th * e2 + ux * ux * e4),
                            nn * ux * uy * e4,
                            nn * (th * e2 + uy * uy * e4)};
+    double fe[kNV];
     for (int r = 0; r < kNV; ++r) {
       double acc = 0.0;
       for (int k = 0; k < kNV; ++k) acc = fma(sp.Minv[r * kNV + k], h[k], acc);
-      out.set((size_t)(s * kNV + r) * I.ps + cell, acc);
+      fe[r] = acc;
+    }
+    if (std::is_same<ST, float>::value && I.om) {
+      float sv[kNV];
+      om_pack(sp, fe, sv);
+      for (int r = 0; r < kNV; ++r) ((float *)out.b)[(size_t)(s * kNV + r) * I.ps + cell] = sv[r];
+    } else {
+      for (int r = 0; r < kNV; ++r) out.set((size_t)(s * kNV + r) * I.ps + cell, fe[r]);
     }
   }
+}
+
+// The 16 values f_i of species s at `cell`, widened to FP64 (reconstructed
+// from OM storage when the buffers hold it).
+template <typename ST>
+__device__ __forceinline__ void cell_f(const InstDev &I, const FV<ST> &f, int s, size_t cell,
+                                       double *out) {
+  if constexpr (std::is_same<ST, float>::value) {
+    if (I.om) {
+      float sv[kNV];
+      for (int i = 0; i < kNV; ++i) sv[i] = ((const float *)f.b)[(size_t)(s * kNV + i) * I.ps + cell];
+      om_unpack(I.sp[s], sv, out);
+      return;
+    }
+  }
+  for (int i = 0; i < kNV; ++i) out[i] = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
 }
 
 // Per-cell species moments in FP64 (dense rows of M).
@@ -1770,9 +2450,11 @@ __device__ __forceinline__ void dense_moments(const InstDev &I, const FV<ST> &f,
                                               size_t cell, int s, double &n, double &jx,
                                               double &jy, double &E) {
   const SpeciesDev &sp = I.sp[s];
+  double fv[kNV];
+  cell_f<ST>(I, f, s, cell, fv);
   n = jx = jy = E = 0.0;
   for (int i = 0; i < kNV; ++i) {
-    const double v = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
+    const double v = fv[i];
     n += v;
     jx = fma(v, sp.M[1 * kNV + i], jx);
     jy = fma(v, sp.M[2 * kNV + i], jy);
@@ -1850,11 +2532,12 @@ __global__ __launch_bounds__(256) void k_noneq(const InstDev *__restrict__ insts
                          nw * (th * e2 + ux * ux * e4),
                          nw * ux * uy * e4,
                          nw * (th * e2 + uy * uy * e4)};
-  double dfv[kNV];
+  double dfv[kNV], fw[kNV];
+  cell_f<ST>(I, f, which, cell, fw);
   for (int r = 0; r < kNV; ++r) {
     double acc = 0.0;
     for (int k = 0; k < kNV; ++k) acc = fma(sp.Minv[r * kNV + k], h[k], acc);
-    dfv[r] = (double)f[(size_t)(which * kNV + r) * I.ps + cell] - acc;
+    dfv[r] = fw[r] - acc;
   }
   for (int row = 4; row < kNV; ++row) {
     double acc = 0.0;
@@ -1906,11 +2589,11 @@ __global__ __launch_bounds__(256) void k_energy(const InstDev *__restrict__ inst
   const double th = Tm * sp.inv_m, u2 = ux * ux + uy * uy;
   const double e2 = (sp.K + 2.0) * th + u2;
   constexpr int rows[4] = {4, 6, 7, 8};  // v_x^2, v_y^2, q v_x, q v_y
-  double mf[4];
+  double mf[4], fw[kNV];
+  cell_f<ST>(I, f, which, cell, fw);
   for (int r = 0; r < 4; ++r) {
     double acc = 0.0;
-    for (int i = 0; i < kNV; ++i)
-      acc = fma(sp.M[rows[r] * kNV + i], (double)f[(size_t)(which * kNV + i) * I.ps + cell], acc);
+    for (int i = 0; i < kNV; ++i) acc = fma(sp.M[rows[r] * kNV + i], fw[i], acc);
     mf[r] = acc;
   }
   const double hm = 0.5 * sp.m;
@@ -2013,6 +2696,62 @@ __global__ __launch_bounds__(256) void k_narrow(const double *__restrict__ src,
   if (k < n) FV<ST>(buf, ntot).set(first + k, (typename Stor<ST>::C)src[k]);
 }
 
+// OM storage transfers: plane i of species s of buffer b as FP64 (dst[cell]);
+// the FP64 distribution staged as planes of stride I.ps, planes 0 .. 8S-1 in
+// lo and the rest in hi, packed into buffer b; and an in-place change of
+// representation of buffer b between FP32 f and OM storage (to_om).
+__global__ __launch_bounds__(256) void k_widen_om(const InstDev *__restrict__ insts, int inst,
+                                                  int b, int s, int i, double *__restrict__ dst) {
+  const InstDev &I = insts[inst];
+  const size_t cells = (size_t)I.nx * I.ny;
+  const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= cells) return;
+  double fv[kNV];
+  cell_f<float>(I, fview<float>(I, b), s, cell, fv);
+  dst[cell] = fv[i];
+}
+__global__ __launch_bounds__(256) void k_pack_om(const InstDev *__restrict__ insts, int inst,
+                                                 const double *__restrict__ lo,
+                                                 const double *__restrict__ hi, int b) {
+  const InstDev &I = insts[inst];
+  const size_t cells = (size_t)I.nx * I.ny;
+  const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= cells) return;
+  const int half = I.S * kNV / 2;
+  float *out = (float *)I.buf[b];
+  for (int s = 0; s < I.S; ++s) {
+    double fv[kNV];
+    float sv[kNV];
+    for (int i = 0; i < kNV; ++i) {
+      const int p = s * kNV + i;
+      fv[i] = p < half ? lo[(size_t)p * I.ps + cell] : hi[(size_t)(p - half) * I.ps + cell];
+    }
+    om_pack(I.sp[s], fv, sv);
+    for (int i = 0; i < kNV; ++i) out[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
+  }
+}
+__global__ __launch_bounds__(256) void k_convert_om(const InstDev *__restrict__ insts, int inst,
+                                                    int b, int to_om) {
+  const InstDev &I = insts[inst];
+  const size_t cells = (size_t)I.nx * I.ny;
+  const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= cells) return;
+  float *buf = (float *)I.buf[b];
+  for (int s = 0; s < I.S; ++s) {
+    float sv[kNV];
+    double fv[kNV];
+    for (int i = 0; i < kNV; ++i) sv[i] = buf[(size_t)(s * kNV + i) * I.ps + cell];
+    if (to_om) {
+      for (int i = 0; i < kNV; ++i) fv[i] = sv[i];
+      om_pack(I.sp[s], fv, sv);
+    } else {
+      om_unpack(I.sp[s], sv, fv);
+      for (int i = 0; i < kNV; ++i) sv[i] = (float)fv[i];
+    }
+    for (int i = 0; i < kNV; ++i) buf[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
+  }
+}
+
 // Non-finite values, or a species density below -1e-12 of the local total.
 template <typename ST>
 __global__ __launch_bounds__(256) void k_check(const InstDev *__restrict__ insts, int inst,
@@ -2025,9 +2764,10 @@ __global__ __launch_bounds__(256) void k_check(const InstDev *__restrict__ insts
   double tot = 0.0, nmin = 0.0;
   bool bad = false;
   for (int s = 0; s < I.S; ++s) {
-    double n = 0.0;
+    double n = 0.0, fv[kNV];
+    cell_f<ST>(I, f, s, cell, fv);
     for (int i = 0; i < kNV; ++i) {
-      const double v = (double)f[(size_t)(s * kNV + i) * I.ps + cell];
+      const double v = fv[i];
       bad |= !isfinite(v);
       n += v;
     }
@@ -2051,6 +2791,8 @@ __global__ __launch_bounds__(64) void k_dpp_probe(int *__restrict__ out) {
   out[320 + l] = (int)shl1(v + 1.0f);
   out[384 + l] = (int)shr1(d + 1.0);
   out[448 + l] = (int)shl1(d + 1.0);
+  out[512 + l] = (int)row_bcast<4>(v);     // lane 16 (l / 16) + 4
+  out[576 + l] = (int)quad_bcast<2>(v);    // lane 4 (l / 4) + 2
 }
 
 // A single wavefront that idles for `ticks` of the constant-rate wall clock
@@ -2083,12 +2825,35 @@ struct FusedLaunch {
   int ntiles, grid, in_idx, fn_idx, out_idx, remap;
   double alpha, beta;
   bool split, pipe, sr, cw;  // split form, row pipeline, stochastic rounding, chain wavefront
+  bool om;                   // FP32-bulk buffers in OM storage
+  uint32_t *ctr;             // step counter of stochastic rounding
   hipStream_t st;
 };
 
 template <typename ST, int S, int LIM, bool RKC>
 static hipError_t launch_fused_t(const FusedLaunch &a) {
   typedef typename Stor<ST>::C T;
+  if constexpr (std::is_same<ST, float>::value) {
+    if (a.om) {
+      if (a.pipe || a.split) return hipErrorInvalidValue;
+#define DBM_OM_LAUNCH(R, C)                                                                     \
+  hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C>), dim3(a.grid),                             \
+                     dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
+                     a.in_idx, a.fn_idx, a.out_idx, (float)a.alpha, a.remap, a.ctr)
+      if constexpr (S <= 3) {
+        if (a.cw) {
+          if (a.sr) DBM_OM_LAUNCH(true, true); else DBM_OM_LAUNCH(false, true);
+          return hipGetLastError();
+        }
+      }
+      if (a.cw) return hipErrorInvalidValue;
+      if (a.sr) DBM_OM_LAUNCH(true, false); else DBM_OM_LAUNCH(false, false);
+#undef DBM_OM_LAUNCH
+      return hipGetLastError();
+    }
+  } else {
+    if (a.om) return hipErrorInvalidValue;
+  }
   if constexpr (!kSplitStore<ST>) {
     if (a.split) {
       hipLaunchKernelGGL((k_fused_split<ST, S, LIM, RKC>), dim3(a.grid), dim3(kWave * 2 * S), 0,
@@ -2100,7 +2865,7 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
 #define DBM_FUSED_LAUNCH(P, R, C)                                                              \
   hipLaunchKernelGGL((k_fused_stage<ST, S, LIM, RKC, P, R, C>), dim3(a.grid),                   \
                      dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
-                     a.in_idx, a.fn_idx, a.out_idx, (T)a.alpha, a.remap)
+                     a.in_idx, a.fn_idx, a.out_idx, (T)a.alpha, a.remap, a.ctr)
   if constexpr (S <= 3) {
     if (a.cw) {
       if (a.sr) DBM_FUSED_LAUNCH(false, true, true); else DBM_FUSED_LAUNCH(false, false, true);
@@ -2146,15 +2911,18 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 // prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
 // sr: stochastic rounding of the stores (FP32-bulk full form only).
 // cw: chain wavefront (full form, S <= 3, no row pipeline).
+// om: OM storage (FP32-bulk full form, no row pipeline); ctr: step counter
+// of stochastic rounding (two words of device memory).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, const InstDev *insts, const Tile *tiles, int ntiles, int grid,
-                        int in_idx, int fn_idx, int out_idx, double alpha, double beta,
-                        hipStream_t st) {
+                        bool cw, bool om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
+                        int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
+                        double beta, hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
-  if (sr && (prec != DBM_FP32_BULK || split)) return hipErrorInvalidValue;
+  if (sr && (prec != DBM_FP32_BULK || split || !ctr)) return hipErrorInvalidValue;
   if (cw && (split || pipe || S > 3)) return hipErrorInvalidValue;
+  if (om && (prec != DBM_FP32_BULK || split || pipe)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
-                      alpha, beta, split, pipe, sr, cw, st};
+                      alpha, beta, split, pipe, sr, cw, om, ctr, st};
   switch (prec) {
     case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
     case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);
@@ -2178,9 +2946,35 @@ constexpr auto k_fused_stage_cw = k_fused_stage<ST, S, LIM, RKC, false, false, t
                default: DBM_PICK1_CW(T, 3); break; }
 // Workgroups of the stage kernel resident per CU (waves_per_cu), for the
 // full form, the split form (split) or the chain-wavefront form (cw).
-hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw,
+template <int S, int LIM, bool RKC, bool CW>
+constexpr auto k_fused_om_nr = k_fused_om<S, LIM, RKC, false, CW>;
+
+hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
                            int *waves_per_cu) {
   const void *fn = nullptr;
+  if (om) {   // OM storage: FP32-bulk full form
+    if (prec != DBM_FP32_BULK || split || (cw && S > 3)) {
+      *waves_per_cu = 0;
+      return hipSuccess;
+    }
+#define DBM_PICK_OM(SS, C)                                                                      \
+  fn = lim == DBM_LIM_MINMOD                                                                   \
+           ? (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, true, C>                   \
+                  : (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, false, C>)                 \
+           : (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, true, C>                     \
+                  : (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, false, C>)
+    if (cw) {
+      switch (S) { case 1: DBM_PICK_OM(1, true); break; case 2: DBM_PICK_OM(2, true); break;
+                   default: DBM_PICK_OM(3, true); break; }
+    } else {
+      switch (S) { case 1: DBM_PICK_OM(1, false); break; case 2: DBM_PICK_OM(2, false); break;
+                   case 3: DBM_PICK_OM(3, false); break; case 4: DBM_PICK_OM(4, false); break;
+                   default: return hipErrorInvalidValue; }
+    }
+#undef DBM_PICK_OM
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn,
+                                                        kWave * (S + (cw ? 1 : 0)), 0);
+  }
   if (prec == DBM_FP32X) split = false;  // full form only
   if (cw) {
     if (S > 3) {
@@ -2237,22 +3031,22 @@ static inline unsigned blocks_for(size_t n, unsigned t) { return (unsigned)((n +
 
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
-                        bool sr, hipStream_t st) {
-  if (sr && prec != DBM_FP32_BULK) return hipErrorInvalidValue;
+                        bool sr, uint32_t *ctr, hipStream_t st) {
+  if (sr && (prec != DBM_FP32_BULK || !ctr)) return hipErrorInvalidValue;
   (void)beta;  // alpha + beta = 1: the combine is res + alpha (f^n - res)
   const dim3 g1(blocks_for(cells, 256)), g2(blocks_for(cells, 256), (unsigned)(S * kNV));
   if (prec == DBM_FP32_BULK) {
     hipLaunchKernelGGL(k_plain_eq<float>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<float>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
-                       out_idx, (float)alpha, (int)rkc, (int)sr);
+                       out_idx, (float)alpha, (int)rkc, (int)sr, ctr);
   } else if (prec == DBM_FP32X) {
     hipLaunchKernelGGL(k_plain_eq<f32x>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<f32x>, g2, dim3(256), 0, st, insts, inst, in_idx, fn_idx,
-                       out_idx, alpha, (int)rkc, 0);
+                       out_idx, alpha, (int)rkc, 0, ctr);
   } else {
     hipLaunchKernelGGL(k_plain_eq<double>, g1, dim3(256), 0, st, insts, inst, in_idx);
     hipLaunchKernelGGL(k_plain_update<double>, g2, dim3(256), 0, st, insts, inst, in_idx,
-                       fn_idx, out_idx, alpha, (int)rkc, 0);
+                       fn_idx, out_idx, alpha, (int)rkc, 0, ctr);
   }
   return hipGetLastError();
 }
@@ -2322,6 +3116,25 @@ hipError_t launch_narrow(int prec, const double *src, void *buf, size_t ntot, si
   return hipGetLastError();
 }
 
+hipError_t launch_widen_om(const InstDev *insts, int inst, size_t cells, int b, int s, int i,
+                           double *dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_widen_om, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts, inst, b, s,
+                     i, dst);
+  return hipGetLastError();
+}
+hipError_t launch_pack_om(const InstDev *insts, int inst, size_t cells, const double *lo,
+                          const double *hi, int b, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_om, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts, inst, lo, hi,
+                     b);
+  return hipGetLastError();
+}
+hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, bool to_om,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_convert_om, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts, inst, b,
+                     (int)to_om);
+  return hipGetLastError();
+}
+
 hipError_t launch_check(int prec, const InstDev *insts, int inst, size_t cells, int in_idx,
                         int *flag, hipStream_t st) {
   DBM_PREC_LAUNCH(prec, k_check, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts,
@@ -2331,18 +3144,35 @@ hipError_t launch_check(int prec, const InstDev *insts, int inst, size_t cells, 
 
 // Streaming copy of n16 16-byte words (grid-stride, non-temporal stores):
 // the achievable-bandwidth reference the stage kernel is compared with.
-__global__ __launch_bounds__(256) void k_copy16(const uint4 *__restrict__ src,
-                                                uint4 *__restrict__ dst, size_t n16) {
+// Each thread keeps W words in flight per iteration (words i, i + stride,
+// ..., so every load instruction of a wavefront reads 1 KiB contiguously).
+template <int W>
+__global__ __launch_bounds__(256) void k_copyw(const uint4 *__restrict__ src,
+                                               uint4 *__restrict__ dst, size_t n16) {
   typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
   const u32x4 *a = (const u32x4 *)src;
   u32x4 *b = (u32x4 *)dst;
-  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (size_t)gridDim.x * 256)
-    __builtin_nontemporal_store(a[i], &b[i]);
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + (W - 1) * stride < n16; i += W * stride) {
+    u32x4 v[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[w] = a[i + w * stride];
+#pragma unroll
+    for (int w = 0; w < W; ++w) __builtin_nontemporal_store(v[w], &b[i + w * stride]);
+  }
+  for (; i < n16; i += stride) __builtin_nontemporal_store(a[i], &b[i]);
 }
 
-hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, hipStream_t st) {
-  hipLaunchKernelGGL(k_copy16, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst,
-                     n16);
+hipError_t launch_copy16(const void *src, void *dst, size_t n16, int grid, int words,
+                         hipStream_t st) {
+  switch (words) {
+    case 1: hipLaunchKernelGGL(k_copyw<1>, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16); break;
+    case 2: hipLaunchKernelGGL(k_copyw<2>, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16); break;
+    case 4: hipLaunchKernelGGL(k_copyw<4>, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16); break;
+    case 8: hipLaunchKernelGGL(k_copyw<8>, dim3(grid), dim3(256), 0, st, (const uint4 *)src, (uint4 *)dst, n16); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

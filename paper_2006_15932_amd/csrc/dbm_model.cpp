@@ -229,6 +229,12 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
   for (int k = 0; k < 16; ++k) {
     sp.MA[k] = mA[k];
     sp.ME[k] = mE[k];
+    sp.iA[k] = iA[k];
+    sp.iE[k] = iE[k];
+  }
+  for (int k = 0; k < 4; ++k) {
+    sp.iB1[k] = iB1[k];
+    sp.iB2[k] = iB2[k];
   }
   // Self-check: the block projection equals the dense inverse.
   for (int trial = 0; trial < 4; ++trial) {
@@ -278,8 +284,37 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
     sp.KB2_f[k] = (float)sp.KB2[k];
     sp.MB1_f[k] = (float)sp.MB1[k];
     sp.MB2_f[k] = (float)sp.MB2[k];
+    sp.wB1_f[k] = (float)(sp.omega * iB1[k]);
+    sp.wB2_f[k] = (float)(sp.omega * iB2[k]);
   }
+  for (int k = 0; k < 16; ++k) sp.wE_f[k] = (float)(sp.omega * iE[k]);
+  // OM storage reference: none until the fields are set (fref = 0).
   return DBM_OK;
+}
+
+// Reference equilibrium of OM storage for one species: fref = f^eq(n_ref, 0,
+// T_ref) = M^{-1} fhat(n_ref, 0, 0, T_ref/m) (fhat at rest: the closed forms
+// listed after Eq.(14) with u = 0), and its A-block moments sref.
+void set_reference(SpeciesDev &sp, double n_ref, double T_ref) {
+  const double th = T_ref * sp.inv_m, K = sp.K;
+  double h[kNV] = {0};
+  h[0] = n_ref;
+  h[3] = n_ref * K * th;
+  h[4] = h[6] = n_ref * th;
+  h[13] = h[15] = n_ref * th * (K + 2.0) * th;
+  for (int r = 0; r < kNV; ++r) {
+    double s = 0.0;
+    for (int c = 0; c < kNV; ++c) s += sp.Minv[r * kNV + c] * h[c];
+    sp.fref[r] = s;
+  }
+  for (int j = 0; j < 4; ++j) sp.sref[j] = 0.0;
+  for (int i = 0; i < kNV; ++i) {
+    const double f = sp.fref[i];
+    sp.sref[0] += sp.M[0 * kNV + i] * f;
+    sp.sref[1] += sp.M[3 * kNV + i] * f;
+    sp.sref[2] += (sp.M[4 * kNV + i] + sp.M[6 * kNV + i]) * f;
+    sp.sref[3] += (sp.M[13 * kNV + i] + sp.M[15 * kNV + i]) * f;
+  }
 }
 
 }  // namespace dbm

@@ -29,6 +29,7 @@ DBM_OPT_BATCH_MODE, DBM_OPT_GRAPH_CHUNK, DBM_OPT_PERSISTENT, DBM_OPT_SPLIT = 5, 
 DBM_OPT_PIPELINE = 9
 DBM_OPT_ROUNDING = 10
 DBM_OPT_CHAIN_WAVE = 11
+DBM_OPT_STORAGE = 12
 
 NV = 16
 
@@ -87,8 +88,11 @@ SIGNATURES = {
     "dbm_get_option": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "dbm_energy_moments": (ctypes.c_int, [_vp, ctypes.c_int, _dp, _dp]),
     "dbm_time_stage_kernel": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
-    "dbm_copy_rate": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int, _vp,
-                                     _dp]),
+    "dbm_copy_rate": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _vp, _dp]),
+    "dbm_state_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int]),
+    "dbm_save_state": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_size_t]),
+    "dbm_load_state": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_size_t]),
     "dbm_last_error": (ctypes.c_char_p, []),
 }
 
@@ -233,28 +237,42 @@ def dbm_get_option(h, option) -> int:
     return v.value
 
 
+def dbm_save_state(h, inst) -> bytes:
+    n = lib().dbm_state_bytes(_vp(h), inst)
+    if n == 0:
+        raise DbmError(DBM_ERR_ARG, last_error())
+    buf = ctypes.create_string_buffer(n)
+    _check(lib().dbm_save_state(_vp(h), inst, ctypes.cast(buf, _vp), n))
+    return buf.raw
+
+
+def dbm_load_state(h, inst, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check(lib().dbm_load_state(_vp(h), inst, ctypes.cast(buf, _vp), len(blob)))
+
+
 def dbm_time_stage_kernel(h, reps) -> float:
     ms = ctypes.c_double(0.0)
     _check(lib().dbm_time_stage_kernel(_vp(h), int(reps), ctypes.byref(ms)))
     return ms.value
 
 
-def dbm_copy_rate(src_ptr, dst_ptr, nbytes, grid, reps, stream_ptr) -> float:
+def dbm_copy_rate(src_ptr, dst_ptr, nbytes, grid, reps, stream_ptr, words=1) -> float:
     """Mean milliseconds of one device-to-device streaming copy of nbytes."""
     ms = ctypes.c_double(0.0)
     _check(lib().dbm_copy_rate(_vp(src_ptr), _vp(dst_ptr), ctypes.c_size_t(nbytes), int(grid),
-                               int(reps), _vp(stream_ptr), ctypes.byref(ms)))
+                               int(words), int(reps), _vp(stream_ptr), ctypes.byref(ms)))
     return ms.value
 
 
-def copy_rate_gbs(nbytes=1 << 30, grid=1024, reps=10, device="cuda:0") -> float:
+def copy_rate_gbs(nbytes=1 << 30, grid=1024, reps=10, device="cuda:0", words=1) -> float:
     """Achievable HBM rate (read + write GB/s) of the library's streaming copy
     on two fresh buffers of nbytes each."""
     import torch
     a = torch.ones(nbytes // 4, dtype=torch.float32, device=device)
     b = torch.empty_like(a)
     st = torch.cuda.current_stream(device)
-    ms = dbm_copy_rate(a.data_ptr(), b.data_ptr(), nbytes, grid, reps, st.cuda_stream)
+    ms = dbm_copy_rate(a.data_ptr(), b.data_ptr(), nbytes, grid, reps, st.cuda_stream, words)
     del a, b
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
@@ -305,6 +323,12 @@ class Simulation:
     def get_f(self, inst=0):
         p = self._p(inst)
         return dbm_get_f(self.h, inst, (p.S, NV, p.ny, p.nx))
+
+    def save_state(self, inst=0) -> bytes:
+        return dbm_save_state(self.h, inst)
+
+    def load_state(self, blob, inst=0):
+        dbm_load_state(self.h, inst, blob)
 
     def step(self, n=1):
         dbm_step(self.h, n)

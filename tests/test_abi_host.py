@@ -117,6 +117,9 @@ def test_null_handle_calls_fail_cleanly():
     assert L.dbm_step(None, 1) == D.DBM_ERR_ARG
     assert L.dbm_destroy(None) == D.DBM_ERR_ARG
     assert L.dbm_moments(None, 0, None, None, None, None) == D.DBM_ERR_ARG
+    assert L.dbm_state_bytes(None, 0) == 0
+    assert L.dbm_save_state(None, 0, None, 0) == D.DBM_ERR_ARG
+    assert L.dbm_load_state(None, 0, None, 0) == D.DBM_ERR_ARG
 
 
 @pytest.mark.parametrize("src,dst,nbytes,grid,reps", [
@@ -133,6 +136,13 @@ def test_copy_rate_rejects_bad_arguments_before_any_launch(src, dst, nbytes, gri
     # the addresses are never dereferenced: validation happens on the host
     with pytest.raises(D.DbmError) as e:
         D.dbm_copy_rate(src, dst, nbytes, grid, reps, 0)
+    assert e.value.code == D.DBM_ERR_ARG
+
+
+@pytest.mark.parametrize("words", [0, 3, 5, 16])
+def test_copy_rate_rejects_unsupported_words_in_flight(words):
+    with pytest.raises(D.DbmError) as e:
+        D.dbm_copy_rate(1 << 20, 1 << 24, 4096, 64, 1, 0, words)
     assert e.value.code == D.DBM_ERR_ARG
 
 

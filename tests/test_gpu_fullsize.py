@@ -37,6 +37,14 @@ def _check(p, precision, steps, tol, nsamples=10, margin_y=0):
     sim.step(steps)
     rho, ux, uy, T = sim.moments()
     sim.close()
+    # The velocity error is normwise (over the whole grid) with the floor of
+    # 1% of the sound speed: the denominator is max(max|u|, 0.01 c_s), where
+    # max|u| over the grid comes from the GPU field (it equals the oracle's to
+    # within the tolerance) and c_s is that of the grid-mean state.
+    rho_t = rho.sum(0)
+    n_t = sum(rho[s] / p.species[s].m for s in range(p.S))
+    cs_mean = math.sqrt(1.4 * float(T.mean()) / float(rho_t.mean() / n_t.mean()))
+    u_den = max(float(np.hypot(ux, uy).max()), 0.01 * cs_mean)
     O.set_threads(8)
     w = 4 * steps + 5
     worst = {"rho": 0.0, "u": 0.0, "T": 0.0}
@@ -47,12 +55,10 @@ def _check(p, precision, steps, tol, nsamples=10, margin_y=0):
         ro, uxo, uyo, To = o.moments(f)
         c = w // 2
         r_g, r_o = rho[:, y, x].sum(), ro[:, c, c].sum()
-        n_o = sum(ro[s, c, c] / p.species[s].m for s in range(p.S))
-        cs = math.sqrt(1.4 * To[c, c] / (r_o / n_o))
-        worst["rho"] = max(worst["rho"], abs(r_g - r_o) / abs(r_o))
-        worst["T"] = max(worst["T"], abs(T[y, x] - To[c, c]) / abs(To[c, c]))
+        worst["rho"] = max(worst["rho"], abs(r_g - r_o) / rho_t.max())
+        worst["T"] = max(worst["T"], abs(T[y, x] - To[c, c]) / T.max())
         du = math.hypot(ux[y, x] - uxo[c, c], uy[y, x] - uyo[c, c])
-        worst["u"] = max(worst["u"], du / max(math.hypot(uxo[c, c], uyo[c, c]), cs))
+        worst["u"] = max(worst["u"], du / u_den)
     print("worst sampled errors", worst, flush=True)
     for k, v in worst.items():
         assert v < tol, (k, v, worst)

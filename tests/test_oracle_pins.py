@@ -488,6 +488,33 @@ def test_specular_walls_conserve_mass_under_gravity():
     assert np.abs(oq.run(fq, 30) - fq).max() < 1e-13 * np.abs(fq).max()
 
 
+def test_specular_walls_exert_no_tangential_force():
+    """Walls reflect only the normal velocity component (specular), so they
+    exert no tangential force: with periodic x, walls in y, no force and a
+    sheared u_x(y), total x-momentum stays constant to rounding while the
+    shear diffuses.  (Bounce-back walls, which reverse both components, pass
+    the mass pin above but drag the layer next to each wall: x-momentum decays.)
+    """
+    sp = [W.make_species(1.0), W.make_species(3.0)]
+    nx, ny = 8, 14
+    y = (np.arange(ny) + 0.5) / ny
+    ux = np.tile((0.12 + 0.1 * np.cos(2 * np.pi * y))[:, None], (1, nx))
+    r = W.splitmix64(7, nx * ny).reshape(ny, nx)
+    base = W.Problem("shear box", nx, ny, sp, bc_x=W.PERIODIC, bc_y=W.WALL)
+    p = base.with_(n_sp=np.stack([0.6 + 0.05 * r, 0.3 + 0.02 * r]), ux=ux,
+                   uy=np.zeros((ny, nx)), T=1.0 + 0.05 * r[::-1])
+    o = O.Oracle(p)
+    f = o.init_equilibrium(*W.fields(p))
+    _, t0 = o.noneq(f, want_delta=False)
+    g = o.run(f, 400)
+    _, t1 = o.noneq(g, want_delta=False)
+    S = p.S
+    scale = t0[:S].sum() * 0.22
+    assert abs(t1[S] - t0[S]) < 1e-13 * scale, (t0[S], t1[S])
+    _, ux1, _, _ = o.moments(g)
+    assert np.abs(ux1[:, 0] - ux[:, 0]).max() > 1e-4   # the shear has diffused
+
+
 def test_create_rejects_bad_input():
     good = W.make_species(1.0)
     with pytest.raises(O.OracleError) as e:
