@@ -268,14 +268,16 @@ __device__ __forceinline__ float sr_add(float f, float d, uint32_t u8) {
 // Step counter of stochastic rounding: ctr[0] is read by every workgroup at
 // the start of a launch; the last workgroup to finish advances it (ctr[1]
 // counts the finished workgroups), so each launch draws new random bits.
+// No fence is needed: every workgroup's read has returned (its value was
+// used) before its increment, the last workgroup writes only after seeing
+// all increments, and the next launch sees the write at the kernel boundary.
+// (A device-scope fence here would write back every XCD's L2 per workgroup.)
 __device__ __forceinline__ void advance_step_counter(uint32_t *ctr, uint32_t step,
                                                      uint32_t nblocks) {
-  __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t done = atomicAdd(&ctr[1], 1u);
+    const uint32_t done =
+        __hip_atomic_fetch_add(&ctr[1], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (done == nblocks - 1) {
-      __threadfence();
       __hip_atomic_store(&ctr[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_store(&ctr[0], step + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1484,9 +1486,10 @@ template <> struct Occ<f32x> { static constexpr int kMinWaves = DBM_MIN_WAVES_F6
 
 // The chain wavefront's part of a tile: after the species wavefronts have
 // published row y0's moments (first barrier), the chain of row k is formed
-// before row k's barrier, from moments published before row k-1's barrier.
-// One barrier per row plus the first, as in fused_tile with CW.
-template <typename T, int S>
+// before row k's barrier, from moments published before row k-1's barrier
+// (NM slots of moments, row k in slot k % NM).  One barrier per row plus the
+// first, as in fused_tile with CW.
+template <typename T, int S, int NM = 2>
 __device__ __forceinline__ void chain_tile(const InstDev &I, int y0, int rows,
                                            double (*mom)[4 * S][kWave],
                                            double (*chn)[kChainRows<S, true>][kWave]) {
@@ -1495,7 +1498,7 @@ __device__ __forceinline__ void chain_tile(const InstDev &I, int y0, int rows,
   const int nrun = rows_run(kSteadyRows<T>, rows);
   for (int k = y0; k < y0 + nrun; ++k) {
     SpC *sp = launder(as_const(I.sp));
-    double(*mb)[kWave] = mom[k & 1];
+    double(*mb)[kWave] = mom[k % NM];
     CellState cs;
     cell_chain<T, S>(I, sp, [&](int q, int sp_) { return mb[q * S + sp_][lane]; }, cs);
     double(*cb)[kWave] = chn[k & 1];
@@ -1835,6 +1838,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
                                               double (*mom)[4 * S][kWave],
                                               double (*chn)[kChainRows<S, CW>][kWave],
                                               float4_t (*hold)[4][kWave]) {
+  // mom: two slots (row parity) without the chain wavefront, three with it
   typedef float T;
   constexpr int kPf = kRingOM;
   const int lane = threadIdx.x & (kWave - 1);
@@ -1863,6 +1867,17 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     const int rr = map_y(r, ny, bcy, flip) * nx;
 #pragma unroll
     for (int i = 0; i < kNV; ++i) dst[i] = bin.value((uint32_t)(rr + lcol), i);
+  };
+  // Chain wavefront: row r's FP64 moments from its stored values, published
+  // as soon as they arrive (row r in slot r % 3 of the moment exchange).
+  auto publish = [&](SpC &me, int r, const T *sv) {
+    double n, jx, jy, E;
+    om_moments(me, sv, n, jx, jy, E);
+    double(*mb)[kWave] = mom[r % 3];
+    mb[0 * S + s][lane] = n;
+    mb[1 * S + s][lane] = jx;
+    mb[2 * S + s][lane] = jy;
+    mb[3 * S + s][lane] = E;
   };
 
   // Halo lanes: lane 16 w + 4 g + q reads slot 4 q + g of column w.
@@ -1936,14 +1951,9 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
         nxv[i] = r1[i];
       }
     }
-    if constexpr (CW) {   // row y0's moments for the chain wavefront's first chain
-      double n0, jx0, jy0, E0;
-      om_moments(me, s0, n0, jx0, jy0, E0);
-      double(*mb)[kWave] = mom[y0 & 1];
-      mb[0 * S + s][lane] = n0;
-      mb[1 * S + s][lane] = jx0;
-      mb[2 * S + s][lane] = jy0;
-      mb[3 * S + s][lane] = E0;
+    if constexpr (CW) {   // rows y0 and y0+1 for the chain wavefront's first chains
+      publish(me, y0, s0);
+      if (y0 + 1 < yend) publish(me, y0 + 1, s1);
       __syncthreads();
     }
   }
@@ -1975,7 +1985,10 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 #pragma unroll
       for (int i = 0; i < kNV; ++i) sn[i] = cur[i];
       om_flip(sn, cflip);
-      if (k + 2 < yend) hold_put(k + 2, sn);
+      if (k + 2 < yend) {
+        hold_put(k + 2, sn);
+        if constexpr (CW) publish(me, k + 2, sn);
+      }
       om_recon(me, sn, fnew);
     }
     T nv[kNV];
@@ -2072,17 +2085,6 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     om_moments(me, sk, n0, jx0, jy0, E0);
     double ux, uy, Tst, dn;
     if constexpr (CW) {
-      if (k + 1 < yend) {   // row k+1's moments for the chain wavefront
-        T s1[kNV];
-        hold_get(k + 1, s1);
-        double n1, jx1, jy1, E1;
-        om_moments(me, s1, n1, jx1, jy1, E1);
-        double(*mb)[kWave] = mom[(k + 1) & 1];
-        mb[0 * S + s][lane] = n1;
-        mb[1 * S + s][lane] = jx1;
-        mb[2 * S + s][lane] = jy1;
-        mb[3 * S + s][lane] = E1;
-      }
       __syncthreads();
       double(*cb)[kWave] = chn[k & 1];
       ux = cb[0][lane];
@@ -2156,7 +2158,7 @@ template <int S, int LIM, bool RKC, bool SR, bool CW>
 __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void k_fused_om(
     const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
     int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr) {
-  __shared__ double mom[2][4 * S][kWave];
+  __shared__ double mom[CW ? 3 : 2][4 * S][kWave];
   __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
   __shared__ float4_t hold[S][kHoldRows][4][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -2165,7 +2167,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
   for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
     const Tile t = tiles[remap ? xcd_remap(v, ntiles) : v];
     if (CW && s == S) {
-      if constexpr (CW) chain_tile<float, S>(insts[t.inst], t.y0, t.rows, mom, chn);
+      if constexpr (CW) chain_tile<float, S, 3>(insts[t.inst], t.y0, t.rows, mom, chn);
     } else {
       fused_tile_om<S, LIM, RKC, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
                                           out_idx, alpha, step, mom, chn,
