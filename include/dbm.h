@@ -190,6 +190,19 @@ int dbm_moments(dbm_handle h, int inst, double *rho_sp, double *ux, double *uy, 
  * in a fixed order (may be NULL).  Synchronises. */
 int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals);
 
+/* For callers that cannot allocate device memory or touch a workspace
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the FP64 domain totals of dbm_noneq_moments ([S+3] = mass^s,
+ * momentum x, y, energy, times dx dy; same kernels, same fixed reduction
+ * order, same values) with the per-workgroup partial sums kept in a fixed
+ * 80 KiB array of the library's own device memory, one per GPU, held until
+ * the process ends, instead of the handle's workspace.  Allocates nothing.
+ * All calls on one GPU share that array (each call rewrites what it reads):
+ * calls that overlap in time on one GPU, from other host threads or
+ * streams, race.  DBM_ERR_ARG if the partial sums would exceed the array
+ * (they cannot for nspecies <= 16) or totals is NULL.  Synchronises. */
+int dbm_noneq_totals_noalloc(dbm_handle h, int inst, double *totals);
+
 /* Translational energies and energy fluxes defined with the nonequilibrium
  * measures (the paragraph after Eqs.(21)-(23)), per species, with
  * M2aa(g) = m sum_i g_i v_ia^2 and M31a(g) = m sum_i g_i (v_i^2 + eta_i^2) v_ia

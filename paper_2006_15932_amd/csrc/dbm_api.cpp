@@ -47,6 +47,11 @@ hipError_t launch_rowsums(const double *src, int nrows, size_t cells, double are
                           double *out, hipStream_t st);
 hipError_t launch_totals(int prec, const InstDev *insts, int inst, int in_idx, int nq,
                          double area, double *partials, double *out, hipStream_t st);
+size_t static_scratch_bytes();
+hipError_t static_scratch_init(int *device);
+void *static_scratch_get(int dev);
+hipError_t launch_totals_static(int prec, const InstDev *insts, int inst, int in_idx, int nq,
+                                double area, void *scratch_ptr, double **out, hipStream_t st);
 hipError_t launch_widen(int prec, const void *buf, size_t ntot, size_t first, double *dst,
                         size_t n, hipStream_t st);
 hipError_t launch_narrow(int prec, const double *src, void *buf, size_t ntot, size_t first,
@@ -238,6 +243,7 @@ struct dbm_s {
   int prec = DBM_FP64;  // DBM_FP64 | DBM_FP32_BULK | DBM_FP32X
   int sr = 0;           // DBM_OPT_ROUNDING: 1 stochastic rounding of FP32 stores
   int om_opt = 0;       // DBM_OPT_STORAGE: 0 OM storage where available, 1 f itself
+  int device = 0;       // device current at dbm_create
   bool om = false;      // the buffers (every instance) hold OM storage
   std::vector<SpeciesDev> tabs;  // host copy of the species tables (OM reference)
   std::vector<std::vector<double>> ref_n;  // OM reference per instance: n_ref^s ...
@@ -784,6 +790,9 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
       (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     return bail(fail(DBM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e)));
   if ((rc = run_probe(h))) return bail(rc);
+  // the fixed scratch of dbm_noneq_totals_noalloc on this device, located now
+  if ((e = static_scratch_init(&h->device)) != hipSuccess)
+    return bail(fail(DBM_ERR_HIP, std::string("scratch symbol: ") + hipGetErrorString(e)));
   if (g_probe_state < 0) h->fused_ok = false;
   if (h->fused_ok) {
     int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, per_cu_om = 0, per_cu_om_cw = 0, dev = 0;
@@ -1011,6 +1020,25 @@ int dbm_noneq_moments(dbm_handle h, int inst, double *delta, double *totals) {
                          h->cfg[inst].dx * h->cfg[inst].dy, part, tot, h->stream));
     HIPCHK(hipMemcpyAsync(totals, tot, sizeof(double) * nq, hipMemcpyDeviceToHost, h->stream));
   }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return DBM_OK;
+}
+
+int dbm_noneq_totals_noalloc(dbm_handle h, int inst, double *totals) {
+  int rc = check_inst(h, inst);
+  if (rc) return rc;
+  if (!totals) return fail(DBM_ERR_ARG, "NULL totals");
+  const int nq = h->S + 3;
+  const size_t need = sizeof(double) * ((size_t)totals_blocks() * nq + nq);
+  if (need > static_scratch_bytes())
+    return fail(DBM_ERR_ARG, "totals need " + std::to_string(need) + " bytes of scratch, more than "
+                                 "the fixed " + std::to_string(static_scratch_bytes()));
+  void *scr = static_scratch_get(h->device);
+  if (!scr) return fail(DBM_ERR_HIP, "fixed scratch not located on the handle's device");
+  double *dev_tot = nullptr;
+  HIPCHK(launch_totals_static(h->prec, h->d_inst(), inst, h->cur, nq,
+                              h->cfg[inst].dx * h->cfg[inst].dy, scr, &dev_tot, h->stream));
+  HIPCHK(hipMemcpyAsync(totals, dev_tot, sizeof(double) * nq, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return DBM_OK;
 }

@@ -28,6 +28,7 @@
 #include <cstdint>
 #include <type_traits>
 #include <cstdlib>
+#include <mutex>
 
 #include "../../include/dbm.h"
 #include "dbm_internal.hpp"
@@ -3101,6 +3102,57 @@ hipError_t launch_totals(int prec, const InstDev *insts, int inst, int in_idx, i
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, st, partials, kTotBlocks, nq, area,
                      out);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Fixed device scratch for the allocation-free totals entry point
+// (dbm_noneq_totals_noalloc): the per-workgroup partial sums of
+// k_totals_partial followed by the S+3 totals.  One copy per GPU, held until
+// the process ends; host code addresses it only through the pointer
+// hipGetSymbolAddress returns for the device (kept per device below).
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = 80 * 1024;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+// Address of each device's `scratch`: looked up once per device, with that
+// device current (the library's set-up, dbm_create), and kept for the
+// entry point, which then only reads the table.
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[64] = {nullptr};
+
+hipError_t static_scratch_init(int *device) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *device = dev;
+  return hipSuccess;
+}
+
+void *static_scratch_get(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  return g_scratch_addr[dev];
+}
+
+// Totals into the fixed scratch (partials, then the nq sums at `out`), or
+// hipErrorInvalidValue when they do not fit.
+hipError_t launch_totals_static(int prec, const InstDev *insts, int inst, int in_idx, int nq,
+                                double area, void *scratch_ptr, double **out, hipStream_t st) {
+  const size_t need = sizeof(double) * ((size_t)kTotBlocks * nq + nq);
+  if (!scratch_ptr || nq < 1 || need > kStaticScratchBytes) return hipErrorInvalidValue;
+  double *part = (double *)scratch_ptr;
+  *out = part + (size_t)kTotBlocks * nq;
+  return launch_totals(prec, insts, inst, in_idx, nq, area, part, *out, st);
 }
 
 // Values first .. first+n-1 of a buffer of ntot values <-> FP64.

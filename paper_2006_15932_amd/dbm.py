@@ -90,6 +90,7 @@ SIGNATURES = {
     "dbm_time_stage_kernel": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "dbm_copy_rate": (ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int, ctypes.c_int,
                                      ctypes.c_int, _vp, _dp]),
+    "dbm_noneq_totals_noalloc": (ctypes.c_int, [_vp, ctypes.c_int, _dp]),
     "dbm_state_bytes": (ctypes.c_size_t, [_vp, ctypes.c_int]),
     "dbm_save_state": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_size_t]),
     "dbm_load_state": (ctypes.c_int, [_vp, ctypes.c_int, _vp, ctypes.c_size_t]),
@@ -220,6 +221,12 @@ def dbm_noneq_moments(h, inst, S, ny, nx, want_delta=True):
     return delta, totals
 
 
+def dbm_noneq_totals_noalloc(h, inst, S):
+    totals = np.zeros(S + 3)
+    _check(lib().dbm_noneq_totals_noalloc(_vp(h), inst, _dptr(totals)))
+    return totals
+
+
 def dbm_energy_moments(h, inst, S, ny, nx, want_fields=True):
     fields = np.zeros((S, 8, ny, nx)) if want_fields else None
     totals = np.zeros((S, 8))
@@ -343,6 +350,9 @@ class Simulation:
     def noneq(self, inst=0, want_delta=True):
         p = self._p(inst)
         return dbm_noneq_moments(self.h, inst, p.S, p.ny, p.nx, want_delta)
+
+    def totals_noalloc(self, inst=0):
+        return dbm_noneq_totals_noalloc(self.h, inst, self._p(inst).S)
 
     def energy(self, inst=0, want_fields=True):
         p = self._p(inst)
