@@ -1838,7 +1838,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
                                               float alpha, uint32_t step,
                                               double (*mom)[4 * S][kWave],
                                               double (*chn)[kChainRows<S, CW>][kWave],
-                                              float4_t (*hold)[4][kWave]) {
+                                              float4_t (*hold)[4][kWave], float (*hhold)[kWave]) {
   // mom: two slots (row parity) without the chain wavefront, three with it
   typedef float T;
   constexpr int kPf = kRingOM;
@@ -1914,6 +1914,10 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     }
   }
   const int hidx1 = lane == kWave - 1 ? 32 * 4 : 16 * 4;
+  // The raw halo of row r is loaded together with stored row r (two rows
+  // ahead, when the tile to the left or right loads the same cache lines as
+  // its own row r) and parked in slot r % 3 of hhold until row r's update.
+  auto halo_load = [&](int r) { return bin.lane_value(hplane, hcol + (uint32_t)(r * nx)); };
 
   // Rows y0-2 .. y0+1: the stencil state of row y0 and the first two rows
   // of the hold.
@@ -1930,7 +1934,11 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     om_flip(sb, fb);
     om_flip(s1, f1);
     hold_put(y0, s0);
-    if (y0 + 1 < yend) hold_put(y0 + 1, s1);
+    hhold[y0 % kHoldRows][lane] = halo_load(y0);
+    if (y0 + 1 < yend) {
+      hold_put(y0 + 1, s1);
+      hhold[(y0 + 1) % kHoldRows][lane] = halo_load(y0 + 1);
+    }
     T ra[kNV], rb[kNV], r1[kNV];
     om_recon(me, sa, ra);
     om_recon(me, sb, rb);
@@ -1959,11 +1967,11 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     }
   }
 
-  // Ring slot of time t: stored row t+2 (with its reflection flag) and the
-  // raw halo of row t.
+  // Ring slot of time t: stored row t+2 (with its reflection flag) and, for
+  // a row of the tile, its raw halo.
   auto issue = [&](int t, T *dst, T &halo, bool &flip) {
     load_row(t + 2, dst, flip);
-    halo = bin.lane_value(hplane, hcol + (uint32_t)(t * nx));
+    halo = t + 2 < yend ? halo_load(t + 2) : T(0);
   };
   T ring[kPf][kNV];
   T hring[kPf];
@@ -1988,6 +1996,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       om_flip(sn, cflip);
       if (k + 2 < yend) {
         hold_put(k + 2, sn);
+        hhold[(k + 2) % kHoldRows][lane] = hcur;
         if constexpr (CW) publish(me, k + 2, sn);
       }
       om_recon(me, sn, fnew);
@@ -2005,11 +2014,12 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     // x-halo of row k as f - fref, and its gathers to the edge lanes.
     T hf;
     {
-      T a = hown * hcur;
-      a = fma(hcA[0], row_bcast<0>(hcur), a);
-      a = fma(hcA[1], row_bcast<4>(hcur), a);
-      a = fma(hcA[2], row_bcast<8>(hcur), a);
-      a = fma(hcA[3], row_bcast<12>(hcur), a);
+      const T hk = hhold[k % kHoldRows][lane];
+      T a = hown * hk;
+      a = fma(hcA[0], row_bcast<0>(hk), a);
+      a = fma(hcA[1], row_bcast<4>(hk), a);
+      a = fma(hcA[2], row_bcast<8>(hk), a);
+      a = fma(hcA[3], row_bcast<12>(hk), a);
       hf = quad_bcast<0>(a);
       hf = fma(hcB, quad_bcast<1>(a), hf);
       hf = fma(hcX, quad_bcast<2>(a), hf);
@@ -2162,6 +2172,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
   __shared__ double mom[CW ? 3 : 2][4 * S][kWave];
   __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
   __shared__ float4_t hold[S][kHoldRows][4][kWave];
+  __shared__ float hhold[S][kHoldRows][kWave];
   const int s = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
   uint32_t step = 0;
   if constexpr (SR) step = __hip_atomic_load(&ctr[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -2172,7 +2183,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
     } else {
       fused_tile_om<S, LIM, RKC, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
                                           out_idx, alpha, step, mom, chn,
-                                          hold[CW && s == S ? 0 : s]);
+                                          hold[CW && s == S ? 0 : s], hhold[CW && s == S ? 0 : s]);
     }
     __syncthreads();
   }
