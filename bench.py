@@ -11,7 +11,9 @@ force, combine -- one launch of the one-pass stage kernel.
 
 Prints ONE JSON line.  `value` is cell-species updates per second over the K
 timed steps (inputs resident in HBM; graph-replayed, one step per graph, the
-graphs captured during the warm-up).  `roofline` is for the one-pass stage
+graphs captured during the W warm-up steps; the first ten or so launches of
+the stage kernel on C4 run up to 15% slower than the rest, so W defaults to
+20; C4 runs at 256 rows per tile, the autotuner's choice, pinned).  `roofline` is for the one-pass stage
 kernel: algorithmic bytes (32 values of f read and written per cell-species
 per Euler step) over its mean launch duration, which is the HIP-event time of
 the timed region (events recorded on the library's stream) divided by the
@@ -43,12 +45,41 @@ METRIC = "cell·species updates/s + % HBM peak, FP32-bulk vs FP64 at stated L∞
 UNIT = "cell-species updates/s"
 
 # HBM bytes per launch of the one-pass stage kernel, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs (profiles/fused_stage_traffic.md), keyed by
+# FETCH_SIZE and WRITE_SIZE runs (profiles/fused_om_c4_counters.md), keyed by
 # workload, with the hash of the kernel code they were taken at (source
 # without comments, see code_text).  Changed kernel code makes the entry stale
 # and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
+    # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
+    # of 9 eager launches at 256 rows per tile (Euler kernels; the source
+    # hash was moved forward over a change to the Runge-Kutta instantiations
+    # only, after checking that the Euler kernels' machine code is unchanged)
+    "c4/fp32/OM": {"source": "7facc8e088162855", "fetch_kib": 2248836.0625,
+                   "write_kib": 4194304.25,
+                   "bytes_per_launch": 2 * 2248836.0625 * 1024 + 4194304.25 * 1024},
+    "c4/fp32/f": {"source": "7facc8e088162855", "fetch_kib": 2577958.0625,
+                  "write_kib": 4194304.0,
+                  "bytes_per_launch": 2 * 2577958.0625 * 1024 + 4194304.0 * 1024},
+    "c4/fp64/f": {"source": "7facc8e088162855", "fetch_kib": 4980753.5625,
+                  "write_kib": 8388609.75,
+                  "bytes_per_launch": 2 * 4980753.5625 * 1024 + 8388609.75 * 1024},
 }
+
+
+# Rows per tile of the timed run (0 = the library's autotuner).  On C4 the
+# autotuner picks 256 (128 and 512 are within 1%); pinning it keeps the
+# tuner's trial launches of the stage kernel out of the run, so that a
+# kernel trace of the run averages the timed configuration only.
+DEFAULT_TILE_ROWS = {"c4": 256}
+
+
+def progress(what: str) -> None:
+    """One line on stderr per finished part of the run (the JSON line alone
+    goes to stdout)."""
+    print("bench: %s done (%.0f s)" % (what, time.time() - T0), file=sys.stderr, flush=True)
+
+
+T0 = time.time()
 
 
 def code_text(src: str) -> str:
@@ -307,11 +338,14 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c4"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "fp32x"])
     ap.add_argument("--mode", default="bench", choices=["bench", "traffic"])
-    ap.add_argument("--tile-rows", type=int, default=0, help="pin rows per tile (0 = autotune)")
+    ap.add_argument("--tile-rows", type=int, default=-1,
+                    help="rows per tile: 0 autotune, -1 the workload's default (C4: 256, the "
+                         "autotuner's choice there, pinned so that every launch of the stage "
+                         "kernel in the run is a launch of the timed configuration)")
     ap.add_argument("--chain-wave", type=int, default=0, choices=[0, 1, 2],
                     help="chain wavefront (S <= 3): 0 autotune, 1 off, 2 on")
     ap.add_argument("--rounding", type=int, default=0, choices=[0, 1],
@@ -325,6 +359,8 @@ def main():
         print("bench.py: one GPU only (the library has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.tile_rows < 0:
+        args.tile_rows = DEFAULT_TILE_ROWS.get(args.workload, 0)
     if args.mode == "traffic":
         return traffic_mode(args)
 
@@ -334,6 +370,7 @@ def main():
                                      args.rounding, args.chain_wave,
                                      None if args.storage < 0 else args.storage)
     sim.close()
+    progress("timed run")
     value = rate(p, args.steps, ms)
     bpl = p.S * p.cells * bytes_per_csu(args.precision, p.scheme)
     achieved = bpl / (kern_ms * 1e-3) / 1e9
@@ -365,6 +402,7 @@ def main():
         line["roofline"]["achievable_copy_gbs"] = cs["best"]["gbs"]
         line["roofline"]["frac_of_achievable"] = achieved / cs["best"]["gbs"]
         extra["copy"] = cs
+        progress("copy sweep")
         # the same grid in other precisions and storages, and with TVD-RK3
         for key, prec, kw in (("fp32_f_storage", "fp32", {"storage": 1}),
                               ("fp32_om_stochastic_rounding", "fp32", {"rounding": 1}),
@@ -375,6 +413,7 @@ def main():
             extra[key] = {"value": rate(q, 10, ms2), "ms_per_launch": k2,
                           "frac": q.S * q.cells * bytes_per_csu(prec, 0) / (k2 * 1e-3) / 1e9
                           / HBM_PEAK_GBS, **i2}
+            progress(key)
         q = p.with_(scheme=1)
         s3, ms3, k3, i3 = gpu_run(q, args.precision, 10, 2)
         s3.close()
@@ -386,6 +425,7 @@ def main():
         sp_, msp, kp, ip = gpu_run(q, "fp64", 5, 2, path=1)
         sp_.close()
         extra["plain_fp64"] = {"value": rate(q, 5, msp), "ms_per_step": msp / 5, **ip}
+        progress("rk3, plain fp64")
         extra["speedup_at_equal_accuracy"] = {
             "fp64_one_pass_vs_plain_fp64": extra["fp64"]["value"] / extra["plain_fp64"]["value"],
         }
@@ -393,6 +433,7 @@ def main():
         extra["c1"] = small_config("c1", "fp32", 2000)
         extra["c1_fp64"] = small_config("c1", "fp64", 1000)
         extra["c1_plain_fp64"] = small_config("c1", "fp64", 500, path=1)
+        progress("c1")
         extra["speedup_at_equal_accuracy"]["c1_fp32_om_vs_plain_fp64"] = (
             extra["c1"]["value"] / extra["c1_plain_fp64"]["value"])
         extra["speedup_at_equal_accuracy"]["c1_fp64_one_pass_vs_plain_fp64"] = (
@@ -406,12 +447,15 @@ def main():
         extra["c2_stochastic_rounding"] = small_config("c2", "fp32", 500, rounding=1)
         extra["c0_fp64"] = small_config("c0", "fp64", 1000)
         extra["c3"] = batched()
+        progress("c2, c0, c3")
         extra["linf_vs_oracle"] = {"sample": "64x64 reacting premix, 200 steps; u gated by "
                                              "max(max|u|, 0.01 c_s), u_cs by max(max|u|, c_s)",
                                    **errors_vs_oracle()}
+        progress("errors vs oracle")
         line["extra"] = extra
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p.with_(precision="fp64"))
+        progress("cpu baseline")
     print(json.dumps(line))
 
 

@@ -2089,6 +2089,14 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       }
       dc[i] = a;
     }
+    // f^n of the Runge-Kutta combine, requested before the moment exchange
+    // and the collision so that their latency hides behind them.
+    const int rkn = k < ny ? rk : (ny - 1) * nx;
+    T fnv[kNV];
+    if constexpr (RKC) {
+#pragma unroll
+      for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rkn + lcol), i);
+    }
     // Collision of row k from its stored values.
     T sk[kNV];
     hold_get(k, sk);
@@ -2126,7 +2134,6 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     om_add_collision(me, d, ds);
     // Stage combine in the stored basis and one store per value.
     T res[kNV];
-    const int rkn = k < ny ? rk : (ny - 1) * nx;
     if constexpr (SR) {
       const uint32_t key = sr_key((uint32_t)(rk + col), s, step, sk);
       uint32_t rb[4];
@@ -2137,14 +2144,14 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 #pragma unroll
       for (int i = 0; i < kNV; ++i) {
         T dd = ds[i];
-        if constexpr (RKC) dd = fma(alpha, (bfn.value((uint32_t)(rkn + lcol), i) - sk[i]) - dd, dd);
+        if constexpr (RKC) dd = fma(alpha, (fnv[i] - sk[i]) - dd, dd);
         res[i] = sr_add(sk[i], dd, rb[i >> 2] >> (8 * (i & 3)));
       }
     } else {
 #pragma unroll
       for (int i = 0; i < kNV; ++i) {
         res[i] = sk[i] + ds[i];
-        if constexpr (RKC) res[i] = fma(alpha, bfn.value((uint32_t)(rkn + lcol), i) - res[i], res[i]);
+        if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
       }
     }
     if (writer) {

@@ -29,5 +29,13 @@ def test_kernel_hash_is_stable_and_stored_entries_are_well_formed():
     h = bench.kernel_source_hash()
     assert h == bench.kernel_source_hash() and len(h) == 16
     for key, entry in bench.MEASURED_TRAFFIC.items():
-        assert key in ("c1/fp32", "c4/fp32")
+        wl, prec, storage = key.split("/")
+        assert wl in ("c1", "c2", "c4") and prec in ("fp32", "fp64", "fp32x")
+        assert storage in ("OM", "f") and (storage == "f" or prec == "fp32")
         assert len(entry["source"]) == 16 and entry["bytes_per_launch"] > 0
+        # FETCH_SIZE counts the kernels' 128 B reads as 64 B: scaled by 2
+        assert entry["bytes_per_launch"] == 1024 * (2 * entry["fetch_kib"] + entry["write_kib"])
+
+
+def test_default_tile_rows_apply_to_the_timed_workload_only():
+    assert bench.DEFAULT_TILE_ROWS == {"c4": 256}
