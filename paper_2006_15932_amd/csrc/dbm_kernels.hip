@@ -2090,10 +2090,13 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       dc[i] = a;
     }
     // f^n of the Runge-Kutta combine, requested before the moment exchange
-    // and the collision so that their latency hides behind them.
+    // and the collision so that their latency hides behind them (with the
+    // chain wavefront the registers for that are not there: requested with
+    // the combine).
+    constexpr bool kEarlyFn = RKC && !CW;
     const int rkn = k < ny ? rk : (ny - 1) * nx;
     T fnv[kNV];
-    if constexpr (RKC) {
+    if constexpr (kEarlyFn) {
 #pragma unroll
       for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rkn + lcol), i);
     }
@@ -2144,14 +2147,20 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 #pragma unroll
       for (int i = 0; i < kNV; ++i) {
         T dd = ds[i];
-        if constexpr (RKC) dd = fma(alpha, (fnv[i] - sk[i]) - dd, dd);
+        if constexpr (RKC) {
+          const T fn = kEarlyFn ? fnv[i] : bfn.value((uint32_t)(rkn + lcol), i);
+          dd = fma(alpha, (fn - sk[i]) - dd, dd);
+        }
         res[i] = sr_add(sk[i], dd, rb[i >> 2] >> (8 * (i & 3)));
       }
     } else {
 #pragma unroll
       for (int i = 0; i < kNV; ++i) {
         res[i] = sk[i] + ds[i];
-        if constexpr (RKC) res[i] = fma(alpha, fnv[i] - res[i], res[i]);
+        if constexpr (RKC) {
+          const T fn = kEarlyFn ? fnv[i] : bfn.value((uint32_t)(rkn + lcol), i);
+          res[i] = fma(alpha, fn - res[i], res[i]);
+        }
       }
     }
     if (writer) {

@@ -118,6 +118,33 @@ def test_om_tile_shape_and_form_do_not_change_bits(case):
                     break
 
 
+def test_four_species_f_storage_ring_tile_rows_do_not_change_bits():
+    """The four-species FP32 Euler form on f storage without the row pipeline
+    keeps three rows of loads in flight: tile heights 1..7 (1, 2 and 3
+    complete rings, the others end mid-ring; 45 rows leave ragged last tiles)
+    give identical bits, within 1e-5 of the oracle (E1)."""
+    p = W.shear_layer(n=70, ny=45, steps=1, precision="fp32")
+    assert p.S == 4
+    opts = {D.DBM_OPT_STORAGE: PLAIN, D.DBM_OPT_PIPELINE: 1}
+    ref = None
+    for rows in (1, 2, 3, 4, 5, 7):
+        sim = gpu_run(p, 30, "fp32", tile_rows=rows, options=opts)
+        assert sim.get_option(D.DBM_OPT_STORAGE) == PLAIN
+        assert sim.get_option(D.DBM_OPT_PIPELINE) == 1
+        assert sim.get_option(D.DBM_OPT_TILE_ROWS) == rows
+        f = sim.get_f()
+        if ref is None:
+            ref = f
+            o, fo = oracle_run(p, 30)
+            e = field_errors(p, sim.moments(), o.moments(fo))
+            print("f storage, 4 species, 30 steps", {k: float("%.3e" % v) for k, v in e.items()},
+                  flush=True)
+            for k in ("rho", "u", "T"):
+                assert e[k] < FP32_TOL, (k, e)
+        else:
+            np.testing.assert_array_equal(f, ref, err_msg="tile rows %d" % rows)
+
+
 def test_conversion_between_representations():
     """Converting the state to f itself and back changes it by FP32 rounding
     only; stepping on OM storage afterwards stays within 1e-5 of the oracle
