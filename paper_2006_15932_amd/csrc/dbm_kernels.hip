@@ -2011,6 +2011,22 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
         nxv[i] = fnew[i];
       }
     }
+    // Collision of row k from its stored values (into sk, d).  With the
+    // chain wavefront it comes before the stencils (the chain is ready at the
+    // row's barrier, and the stencils' registers are free then: no spills);
+    // without it after them (measured faster for four species, where each
+    // wavefront forms the chain after the barrier).
+    T sk[kNV];
+    T d[kNV];
+    if constexpr (CW) {
+      hold_get(k, sk);
+      double n0, jx0, jy0, E0;
+      om_moments(me, sk, n0, jx0, jy0, E0);
+      __syncthreads();
+      double(*cb)[kWave] = chn[k & 1];
+      const double ux = cb[0][lane], uy = cb[1][lane], Tst = cb[2][lane], dn = cb[3 + s][lane];
+      collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
+    }
     // x-halo of row k as f - fref, and its gathers to the edge lanes.
     T hf;
     {
@@ -2100,20 +2116,11 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 #pragma unroll
       for (int i = 0; i < kNV; ++i) fnv[i] = bfn.value((uint32_t)(rkn + lcol), i);
     }
-    // Collision of row k from its stored values.
-    T sk[kNV];
-    hold_get(k, sk);
-    double n0, jx0, jy0, E0;
-    om_moments(me, sk, n0, jx0, jy0, E0);
-    double ux, uy, Tst, dn;
-    if constexpr (CW) {
-      __syncthreads();
-      double(*cb)[kWave] = chn[k & 1];
-      ux = cb[0][lane];
-      uy = cb[1][lane];
-      Tst = cb[2][lane];
-      dn = cb[3 + s][lane];
-    } else {
+    if constexpr (!CW) {
+      hold_get(k, sk);
+      double n0, jx0, jy0, E0;
+      om_moments(me, sk, n0, jx0, jy0, E0);
+      double ux, uy, Tst, dn;
       double(*mb)[kWave] = mom[k & 1];
       mb[0 * S + s][lane] = n0;
       mb[1 * S + s][lane] = jx0;
@@ -2129,9 +2136,8 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       ux = cs.ux;
       uy = cs.uy;
       Tst = cs.Tst;
+      collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
     }
-    T d[kNV];
-    collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
     T ds[kNV];
     om_project(me, dc, ds);
     om_add_collision(me, d, ds);
