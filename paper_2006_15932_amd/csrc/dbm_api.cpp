@@ -17,9 +17,9 @@
 
 namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
-void set_reference(SpeciesDev &sp, double n_ref, double T_ref);
+void om_reference(const SpeciesDev &sp, double n_ref, double T_ref, double *out);
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, bool om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
+                        bool cw, int om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
                         int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
                         double beta, hipStream_t st);
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
@@ -95,7 +95,7 @@ struct Layout {
   size_t sp_off = 0, inst_off = 0, tile_off = 0, part_off = 0, tot_off = 0, flag_off = 0,
          probe_off = 0, ctr_off = 0;
   size_t tile_cap = 0;
-  std::vector<size_t> buf_off[3], scratch_off;
+  std::vector<size_t> buf_off[3], scratch_off, rref_off, dref_off, orec_off;
   size_t total = 0;
 };
 
@@ -207,6 +207,18 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   off = align_up(off + sizeof(uint32_t) * 4);
   for (int b = 0; b < 3; ++b) L.buf_off[b].resize(ninst);
   L.scratch_off.resize(ninst);
+  L.rref_off.resize(ninst);
+  L.dref_off.resize(ninst);
+  L.orec_off.resize(ninst);
+  for (int k = 0; k < ninst; ++k) {
+    // OM storage references per species and grid row (InstDev::rref, dref)
+    L.rref_off[k] = off;
+    off = align_up(off + sizeof(double) * (size_t)S * cfgs[k].ny * kRowRef);
+    L.dref_off[k] = off;
+    off = align_up(off + sizeof(float) * (size_t)S * (cfgs[k].ny + 4) * 4);
+    L.orec_off[k] = off;
+    off = align_up(off + sizeof(uint32_t) * (size_t)S * cfgs[k].ny * kRowRec);
+  }
   for (int k = 0; k < ninst; ++k) {
     const size_t cells = (size_t)cfgs[k].nx * cfgs[k].ny;
     const size_t fbytes = (size_t)S * kNV * pstride(cfgs[k]) * esize(cfgs[k]);
@@ -245,9 +257,20 @@ struct dbm_s {
   int om_opt = 0;       // DBM_OPT_STORAGE: 0 OM storage where available, 1 f itself
   int device = 0;       // device current at dbm_create
   bool om = false;      // the buffers (every instance) hold OM storage
-  std::vector<SpeciesDev> tabs;  // host copy of the species tables (OM reference)
-  std::vector<std::vector<double>> ref_n;  // OM reference per instance: n_ref^s ...
-  std::vector<double> ref_T;               // ... and T_ref
+  std::vector<SpeciesDev> tabs;  // host copy of the species tables
+  // OM storage reference per instance and grid row: n_ref^s [s * ny + y] and
+  // T_ref [y]; rowref[k]: instance k's references differ between rows (else
+  // one reference serves the grid)
+  std::vector<std::vector<double>> ref_n, ref_T;
+  std::vector<char> rowref;
+  // stage-kernel form of the storage: 0 f itself, 1 OM storage with one
+  // reference per grid, 2 with references per row (some instance needs them)
+  int om_mode() const {
+    if (!om) return 0;
+    for (char r : rowref)
+      if (r) return 2;
+    return 1;
+  }
   std::vector<dbm_config> cfg;
   std::vector<std::vector<dbm_species>> species;
   std::vector<dbm_reaction> reaction;
@@ -326,16 +349,16 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
     if (h->batch_mode == 0) {
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
-      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw, h->om,
-                          ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx,
-                          alpha, beta, st));
+      HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
+                          h->om_mode(), ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
+                          out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
         HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                            h->om, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx, fn_idx,
-                            out_idx, alpha, beta, st));
+                            h->om_mode(), ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
+                            fn_idx, out_idx, alpha, beta, st));
       }
     }
   } else {
@@ -426,8 +449,8 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    (((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 2 +
-                        (h->om ? 1 : 0)};
+                    (((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 3 +
+                        h->om_mode()};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -615,19 +638,104 @@ int sync_storage(dbm_handle h) {
   return DBM_OK;
 }
 
-// OM storage reference of instance inst: an equilibrium at rest with the
-// least density of each species and the least temperature of the initial
-// state (deviations stay non-negative and a species absent somewhere keeps no
-// offset); non-finite or negative entries are taken as 0 (no offset).
-int set_om_reference(dbm_handle h, int inst, const std::vector<double> &n_min, double T_min) {
-  std::vector<double> n(n_min);
+// y-boundary map of the host (the kernels' map_y): the grid row that holds
+// row r, and whether it is reflected.
+int host_map_y(int r, int ny, int bc, bool &flip) {
+  flip = false;
+  if (r >= 0 && r < ny) return r;
+  if (bc == BC_PERIODIC) return ((r % ny) + ny) % ny;
+  if (bc == BC_OUTFLOW) return r < 0 ? 0 : ny - 1;
+  // specular wall: reflection about the wall face, repeated if needed
+  const int p = 2 * ny;
+  int q = ((r % p) + p) % p;
+  if (q >= ny) {
+    q = p - 1 - q;
+    flip = true;
+  }
+  return q;
+}
+
+// OM storage reference of instance inst, per grid row: an equilibrium at
+// rest with the row means of each species' density and of the temperature
+// of the state being set (n_row [s * ny + y], T_row [y]; non-finite or
+// negative entries are taken as 0: no offset).  Builds and uploads the FP64
+// references with their A-block moments and the FP32 differences between
+// consecutive rows, one per velocity group (an equilibrium at rest has one
+// value per group), rows outside the grid as the y boundary maps them, and
+// the one-pass kernel's per-row records of both (InstDev::orec).
+int set_om_reference(dbm_handle h, int inst, const std::vector<double> &n_row,
+                     const std::vector<double> &T_row) {
+  const int S = h->S, ny = h->cfg[inst].ny, bcy = h->cfg[inst].bc_y;
+  std::vector<double> n(n_row), T(T_row);
   for (auto &v : n)
     if (!std::isfinite(v) || v < 0.0) v = 0.0;
-  const double T = (std::isfinite(T_min) && T_min > 0.0) ? T_min : 0.0;
-  for (int s = 0; s < h->S; ++s) set_reference(h->tabs[(size_t)inst * h->S + s], n[s], T);
+  for (auto &v : T)
+    if (!std::isfinite(v) || v < 0.0) v = 0.0;
+  // References per row only where the rows differ by more than 1e-3 of the
+  // mean (density of a species or temperature); otherwise every row takes
+  // the grid's mean, and the stage kernel's form without the per-row terms
+  // runs.
+  auto spread = [&](const double *v) {
+    double m = 0.0, d = 0.0;
+    for (int y = 0; y < ny; ++y) m += v[y] / ny;
+    for (int y = 0; y < ny; ++y) d = std::fmax(d, std::fabs(v[y] - m));
+    return std::make_pair(m, d > 1e-3 * m);
+  };
+  bool rows = spread(T.data()).second;
+  for (int s = 0; s < S; ++s) rows = rows || spread(&n[(size_t)s * ny]).second;
+  if (!rows) {
+    const double tm = spread(T.data()).first;
+    for (int y = 0; y < ny; ++y) T[y] = tm;
+    for (int s = 0; s < S; ++s) {
+      const double nm = spread(&n[(size_t)s * ny]).first;
+      for (int y = 0; y < ny; ++y) n[(size_t)s * ny + y] = nm;
+    }
+  }
+  if ((h->rowref[inst] != 0) != rows) {   // another kernel form: graphs are stale
+    h->rowref[inst] = rows ? 1 : 0;
+    clear_graphs(h);
+  }
+  std::vector<double> rr((size_t)S * ny * kRowRef);
+  std::vector<float> dr((size_t)S * (ny + 4) * 4);
+  std::vector<uint32_t> rec((size_t)S * ny * kRowRec, 0u);
+  for (int s = 0; s < S; ++s) {
+    const SpeciesDev &sp = h->tabs[(size_t)inst * S + s];
+    for (int y = 0; y < ny; ++y)
+      om_reference(sp, n[(size_t)s * ny + y], T[y], &rr[((size_t)s * ny + y) * kRowRef]);
+    // fref of group g at row r as the boundary map sees it (a reflected row
+    // is the mirrored row, whose groups are unchanged by the reflection)
+    auto fref = [&](int r, int g) {
+      bool flip;
+      const int q = host_map_y(r, ny, bcy, flip);
+      return rr[((size_t)s * ny + q) * kRowRef + 4 * g];
+    };
+    for (int r = -2; r <= ny + 1; ++r)
+      for (int g = 0; g < 4; ++g)
+        dr[((size_t)s * (ny + 4) + r + 2) * 4 + g] = (float)(fref(r + 1, g) - fref(r, g));
+    for (int y = 0; y < ny; ++y) {
+      uint32_t *w = &rec[((size_t)s * ny + y) * kRowRec];
+      std::memcpy(w, &dr[((size_t)s * (ny + 4) + y + 2) * 4], sizeof(float) * 8);
+      std::memcpy(w + 8, &rr[((size_t)s * ny + y) * kRowRef + kNV], sizeof(double) * 4);
+      if (y + 2 < ny) std::memcpy(w + 16, &rr[((size_t)s * ny + y + 2) * kRowRef + kNV],
+                                  sizeof(double) * 2);
+    }
+  }
+  // the single reference's moments also sit in the species tables (the
+  // stage kernel's form without per-row references reads them there)
+  for (int s = 0; s < S; ++s)
+    for (int j = 0; j < 4; ++j)
+      h->tabs[(size_t)inst * S + s].sref[j] = rr[((size_t)s * ny) * kRowRef + kNV + j];
+  if (int rc = upload_tables(h, inst)) return rc;
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.rref_off[inst], rr.data(), sizeof(double) * rr.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.dref_off[inst], dr.data(), sizeof(float) * dr.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(h->ws + h->L.orec_off[inst], rec.data(), sizeof(uint32_t) * rec.size(),
+                        hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
   h->ref_n[inst] = n;
   h->ref_T[inst] = T;
-  return upload_tables(h, inst);
+  return DBM_OK;
 }
 
 // Checkpoint blob: this header, then the instance's current f buffer as
@@ -637,9 +745,13 @@ struct StateHeader {
   uint64_t magic;
   int32_t prec, om, S, nx, ny, sr;
   uint64_t buffer_bytes;
-  double ref_n[kMaxSpecies], ref_T;
   uint32_t ctr[2];
 };
+// ... followed by the OM references of the rows, (S + 1) x ny FP64 values
+// (n_ref^s per row, then T_ref per row), then the buffer.
+size_t state_ref_bytes(dbm_handle h, int inst) {
+  return sizeof(double) * (size_t)(h->S + 1) * h->cfg[inst].ny;
+}
 constexpr uint64_t kStateMagic = 0x4554415453424D44ULL;   // "DBMSTATE" in little-endian bytes
 size_t buffer_bytes(dbm_handle h, int inst) {
   return (size_t)h->S * kNV * h->ps(inst) * esize(h->cfg[inst]);
@@ -693,8 +805,13 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
                                        " bytes");
   dbm_s *h = new dbm_s();
   h->tabs = tabs;
-  h->ref_n.assign(ninst, std::vector<double>(cfgs[0].nspecies, 0.0));
-  h->ref_T.assign(ninst, 0.0);
+  h->ref_n.resize(ninst);
+  h->ref_T.resize(ninst);
+  h->rowref.assign(ninst, 0);
+  for (int k = 0; k < ninst; ++k) {
+    h->ref_n[k].assign((size_t)cfgs[0].nspecies * cfgs[k].ny, 0.0);
+    h->ref_T[k].assign((size_t)cfgs[k].ny, 0.0);
+  }
   h->ninst = ninst;
   h->S = cfgs[0].nspecies;
   h->fp32 = cfgs[0].precision == DBM_FP32_BULK;
@@ -731,6 +848,9 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     d.ps = pstride(cfgs[k]);
     d.scratch = h->ws + L.scratch_off[k];
     d.sp = (const SpeciesDev *)(h->ws + L.sp_off) + (size_t)k * h->S;
+    d.rref = (const double *)(h->ws + L.rref_off[k]);
+    d.dref = (const float *)(h->ws + L.dref_off[k]);
+    d.orec = (const uint32_t *)(h->ws + L.orec_off[k]);
     d.nx = cfgs[k].nx;
     d.ny = cfgs[k].ny;
     d.bcx = cfgs[k].bc_x;
@@ -789,6 +909,10 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
                           hipMemcpyHostToDevice, h->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(h->stream)) != hipSuccess)
     return bail(fail(DBM_ERR_HIP, std::string("table upload: ") + hipGetErrorString(e)));
+  // OM storage references: none (zero) until the fields are set
+  if (h->prec == DBM_FP32_BULK)
+    for (int k = 0; k < ninst; ++k)
+      if ((rc = set_om_reference(h, k, h->ref_n[k], h->ref_T[k]))) return bail(rc);
   if ((rc = run_probe(h))) return bail(rc);
   // the fixed scratch of dbm_noneq_totals_noalloc on this device, located now
   if ((e = static_scratch_init(&h->device)) != hipSuccess)
@@ -844,13 +968,20 @@ int dbm_set_fields(dbm_handle h, int inst, const double *n_sp, const double *ux,
   if (rc) return rc;
   if (!n_sp || !ux || !uy || !T) return fail(DBM_ERR_ARG, "NULL field array");
   const size_t cells = h->cells(inst), S = h->S;
-  if (h->prec == DBM_FP32_BULK) {   // OM storage reference: least n^s and T, at rest
-    std::vector<double> nm(S, HUGE_VAL);
-    double tm = HUGE_VAL;
-    for (size_t s = 0; s < S; ++s)
-      for (size_t c = 0; c < cells; ++c) nm[s] = std::fmin(nm[s], n_sp[s * cells + c]);
-    for (size_t c = 0; c < cells; ++c) tm = std::fmin(tm, T[c]);
-    if ((rc = set_om_reference(h, inst, nm, tm))) return rc;
+  if (h->prec == DBM_FP32_BULK) {   // OM storage reference: row means of n^s and T, at rest
+    const size_t nx = h->cfg[inst].nx, ny = h->cfg[inst].ny;
+    std::vector<double> nr(S * ny, 0.0), tr(ny, 0.0);
+    for (size_t y = 0; y < ny; ++y) {
+      for (size_t s = 0; s < S; ++s) {
+        double a = 0.0;
+        for (size_t x = 0; x < nx; ++x) a += n_sp[s * cells + y * nx + x];
+        nr[s * ny + y] = a / (double)nx;
+      }
+      double a = 0.0;
+      for (size_t x = 0; x < nx; ++x) a += T[y * nx + x];
+      tr[y] = a / (double)nx;
+    }
+    if ((rc = set_om_reference(h, inst, nr, tr))) return rc;
   }
   if ((rc = reset_counters(h))) return rc;
   double *stage = (double *)h->inst[inst].scratch;
@@ -870,12 +1001,13 @@ int dbm_set_f(dbm_handle h, int inst, const double *f) {
   const size_t cells = h->cells(inst), nplanes = (size_t)h->S * kNV, ps = h->ps(inst);
   void *dst = h->inst[inst].buf[h->cur];
   if (h->prec == DBM_FP32_BULK) {
-    // OM storage reference from f: least density of each species and least
-    // mixture temperature (moments n, j, E of every cell, FP64).
+    // OM storage reference from f: row means of each species' density and of
+    // the mixture temperature (moments n, j, E of every cell, FP64).
     const int S = h->S;
-    std::vector<double> nm(S, HUGE_VAL);
-    double tm = HUGE_VAL;
+    const size_t nx = h->cfg[inst].nx, ny = h->cfg[inst].ny;
+    std::vector<double> nr((size_t)S * ny, 0.0), tr(ny, 0.0);
     for (size_t c = 0; c < cells; ++c) {
+      const size_t y = c / nx;
       double rho = 0, px = 0, py = 0, e = 0, kn = 0;
       for (int s = 0; s < S; ++s) {
         const SpeciesDev &sp = h->tabs[(size_t)inst * S + s];
@@ -887,16 +1019,16 @@ int dbm_set_f(dbm_handle h, int inst, const double *f) {
           jy += v * sp.M[2 * kNV + i];
           E += v * sp.M[3 * kNV + i];
         }
-        nm[s] = std::fmin(nm[s], n);
+        nr[(size_t)s * ny + y] += n / (double)nx;
         rho += sp.m * n;
         px += sp.m * jx;
         py += sp.m * jy;
         e += sp.m * E;
         kn += sp.K * n;
       }
-      if (rho != 0.0 && kn != 0.0) tm = std::fmin(tm, (e - (px * px + py * py) / rho) / kn);
+      if (rho != 0.0 && kn != 0.0) tr[y] += (e - (px * px + py * py) / rho) / kn / (double)nx;
     }
-    if ((rc = set_om_reference(h, inst, nm, tm))) return rc;
+    if ((rc = set_om_reference(h, inst, nr, tr))) return rc;
   }
   if ((rc = reset_counters(h))) return rc;
   if (h->prec == DBM_FP64) {
@@ -1194,7 +1326,7 @@ int dbm_copy_rate(const void *src, void *dst, size_t bytes, int grid, int words,
 
 size_t dbm_state_bytes(dbm_handle h, int inst) {
   if (check_inst(h, inst)) return 0;
-  return sizeof(StateHeader) + buffer_bytes(h, inst);
+  return sizeof(StateHeader) + state_ref_bytes(h, inst) + buffer_bytes(h, inst);
 }
 
 int dbm_save_state(dbm_handle h, int inst, void *dst, size_t bytes) {
@@ -1211,13 +1343,15 @@ int dbm_save_state(dbm_handle h, int inst, void *dst, size_t bytes) {
   hd.ny = h->cfg[inst].ny;
   hd.sr = h->sr;
   hd.buffer_bytes = buffer_bytes(h, inst);
-  for (int s = 0; s < h->S; ++s) hd.ref_n[s] = h->ref_n[inst][s];
-  hd.ref_T = h->ref_T[inst];
+  const size_t rb = state_ref_bytes(h, inst);
   HIPCHK(hipMemcpyAsync(hd.ctr, h->d_ctr(false), sizeof(hd.ctr), hipMemcpyDeviceToHost, h->stream));
-  HIPCHK(hipMemcpyAsync((char *)dst + sizeof(StateHeader), h->inst[inst].buf[h->cur],
+  HIPCHK(hipMemcpyAsync((char *)dst + sizeof(StateHeader) + rb, h->inst[inst].buf[h->cur],
                         hd.buffer_bytes, hipMemcpyDeviceToHost, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   std::memcpy(dst, &hd, sizeof(hd));
+  const size_t nn = sizeof(double) * h->ref_n[inst].size();
+  std::memcpy((char *)dst + sizeof(StateHeader), h->ref_n[inst].data(), nn);
+  std::memcpy((char *)dst + sizeof(StateHeader) + nn, h->ref_T[inst].data(), rb - nn);
   return DBM_OK;
 }
 
@@ -1231,9 +1365,13 @@ int dbm_load_state(dbm_handle h, int inst, const void *src, size_t bytes) {
       hd.nx != h->cfg[inst].nx || hd.ny != h->cfg[inst].ny ||
       hd.buffer_bytes != buffer_bytes(h, inst) || bytes < dbm_state_bytes(h, inst))
     return fail(DBM_ERR_ARG, "state blob does not match this handle's configuration");
-  std::vector<double> nm(hd.ref_n, hd.ref_n + h->S);
-  if ((rc = set_om_reference(h, inst, nm, hd.ref_T))) return rc;
-  HIPCHK(hipMemcpyAsync(h->inst[inst].buf[h->cur], (const char *)src + sizeof(StateHeader),
+  const size_t ny = h->cfg[inst].ny, rb = state_ref_bytes(h, inst);
+  std::vector<double> nr((size_t)h->S * ny), tr(ny);
+  std::memcpy(nr.data(), (const char *)src + sizeof(StateHeader), sizeof(double) * nr.size());
+  std::memcpy(tr.data(), (const char *)src + sizeof(StateHeader) + sizeof(double) * nr.size(),
+              sizeof(double) * ny);
+  if ((rc = set_om_reference(h, inst, nr, tr))) return rc;
+  HIPCHK(hipMemcpyAsync(h->inst[inst].buf[h->cur], (const char *)src + sizeof(StateHeader) + rb,
                         hd.buffer_bytes, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(h->d_ctr(false), hd.ctr, sizeof(hd.ctr), hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));

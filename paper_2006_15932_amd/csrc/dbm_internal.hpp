@@ -58,14 +58,13 @@ struct SpeciesDev {
   //   s[4..7]   B_a, B_b, B_c, B_d   (orbit alternating sums of f)
   //   s[8..11]  X_a .. X_d           (orbit sums signed by v_x)
   //   s[12..15] Y_a .. Y_d           (orbit sums signed by v_y)
-  // with fref = f^eq(n_ref, 0, T_ref) a fixed equilibrium at rest, whose B, X
-  // and Y vanish.  iA, iB1, iB2, iE are the plain inverses of the blocks
-  // (moments -> orbit components); the FP32 copies of iB and iE carry the
-  // factor omega = dt/tau of the collision.
-  double fref[kNV];      // reference distribution f^eq(n_ref, 0, T_ref)
-  double sref[4];        // its A-block moments
+  // with fref = f^eq(n_ref, 0, T_ref) an equilibrium at rest, whose B, X and Y
+  // vanish, fixed per grid row (InstDev::rref).  iA, iB1, iB2, iE are the
+  // plain inverses of the blocks (moments -> orbit components); the FP32
+  // copies of iB and iE carry the factor omega = dt/tau of the collision.
   double iA[16], iB1[4], iB2[4], iE[16];
   float wB1_f[4], wB2_f[4], wE_f[16];
+  double sref[4];        // the A-block moments of fref when one reference serves the grid
 };
 
 // Elements from one plane of an f buffer to the next: the nx*ny cells plus
@@ -100,7 +99,23 @@ struct InstDev {
   double dt, dx, dy;
   int lim;
   int om;                // FP32-bulk buffers hold OM storage (see SpeciesDev)
+  // OM storage references, one per species and grid row (set with the
+  // fields): rref[(s * ny + y) * kRowRef + 0..15] = fref of row y (FP64),
+  // + 16..19 = its A-block moments sref; dref[(s * (ny + 4) + y + 2) * 4 +
+  // g] = fref(row y+1) - fref(row y) of the planes of velocity group g (equal
+  // at rest) rounded once to FP32, for y = -2 .. ny+1 with the rows outside
+  // the grid mapped as the y boundary maps them (the stencil's differences
+  // between rows add it).
+  const double *rref;
+  const float *dref;
+  // The same per species and grid row y as one record of kRowRec 32-bit
+  // words for the one-pass kernel: the group differences of rows y and y+1
+  // (words 0..3, 4..7), sref of row y (FP64, words 8..15) and the first two
+  // sref of row y+2 (words 16..19; zero past the grid).
+  const uint32_t *orec;
 };
+constexpr int kRowRef = kNV + 4;
+constexpr int kRowRec = 20;
 
 // One tile: a wavefront marches `rows` rows of 64 columns starting at (x0, y0).
 struct Tile {

@@ -1675,10 +1675,11 @@ __device__ __forceinline__ void om_add_collision(SpC &sp, const float *d, float 
 
 // FP64 species moments from the stored values: n and E are the first two
 // A-block moments plus the reference's, j = sum_g v_g (X_g, Y_g).
-__device__ __forceinline__ void om_moments(SpC &sp, const float *s, double &n, double &jx,
-                                           double &jy, double &E) {
-  n = (double)s[0] + sp.sref[0];
-  E = (double)s[1] + sp.sref[1];
+template <typename P>
+__device__ __forceinline__ void om_moments(SpC &sp, P sref, const float *s, double &n,
+                                           double &jx, double &jy, double &E) {
+  n = (double)s[0] + sref[0];
+  E = (double)s[1] + sref[1];
   jx = jy = 0.0;
 #pragma unroll
   for (int g = 0; g < 4; ++g) {
@@ -1691,7 +1692,9 @@ __device__ __forceinline__ void om_moments(SpC &sp, const float *s, double &n, d
 // storage): the conserved rows 0, 1, 8, 12 and the A-block rows 2, 3 are
 // differenced in FP64 against the stored moments plus the reference's; the
 // B, X and Y rows in FP32, where both terms are small near rest.
-__device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, const float *s,
+template <typename P>
+__device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, P sref,
+                                                 const float *s,
                                                  double n, double jx, double jy, double E,
                                                  double ns, double ux, double uy, double Tst,
                                                  float *d) {
@@ -1700,8 +1703,8 @@ __device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, cons
   eq_rhs<float>((float)ns, (float)ux, (float)uy, (float)th, (float)K, r);
   const double e2 = (K + 2.0) * th + u2, e4 = (K + 4.0) * th + u2;
   double d0 = ns - n, d1 = ns * fma(K, th, u2) - E, d8 = ns * ux - jx, d12 = ns * uy - jy;
-  double d2 = (ns * (2.0 * th + u2) - sp.sref[2]) - (double)s[2];
-  double d3 = (ns * fma(2.0 * th, e2, u2 * e4) - sp.sref[3]) - (double)s[3];
+  double d2 = (ns * (2.0 * th + u2) - sref[2]) - (double)s[2];
+  double d3 = (ns * fma(2.0 * th, e2, u2 * e4) - sref[3]) - (double)s[3];
   const bool force = I.force && n > 1e-300;
   double fd[16];
   if (force) {
@@ -1756,11 +1759,12 @@ __device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, cons
 
 // FP64 conversions between f and OM storage (initialisation, transfers,
 // diagnostics and changes of representation).
-__device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *f, float *s) {
+__device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *fref, const double *f,
+                                        float *s) {
   double A[4];
   for (int g = 0; g < 4; ++g) {
-    const double c0 = f[4 * g] - sp.fref[4 * g], c1 = f[4 * g + 1] - sp.fref[4 * g + 1];
-    const double c2 = f[4 * g + 2] - sp.fref[4 * g + 2], c3 = f[4 * g + 3] - sp.fref[4 * g + 3];
+    const double c0 = f[4 * g] - fref[4 * g], c1 = f[4 * g + 1] - fref[4 * g + 1];
+    const double c2 = f[4 * g + 2] - fref[4 * g + 2], c3 = f[4 * g + 3] - fref[4 * g + 3];
     A[g] = (c0 + c2) + (c1 + c3);
     s[4 + g] = (float)((c0 + c2) - (c1 + c3));
     if ((g & 1) == 0) {
@@ -1777,7 +1781,8 @@ __device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *f, f
     s[j] = (float)m;
   }
 }
-__device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const float *s, double *f) {
+__device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const double *fref, const float *s,
+                                          double *f) {
   for (int g = 0; g < 4; ++g) {
     double A = 0.0;
     for (int j = 0; j < 4; ++j) A = fma(sp.iA[g * 4 + j], (double)s[j], A);
@@ -1790,8 +1795,19 @@ __device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const float *s, 
       const double sm = 0.25 * (X + Y), df = 0.25 * (X - Y);
       o[0] = p + sm; o[1] = m - df; o[2] = p - sm; o[3] = m + df;
     }
-    for (int k = 0; k < 4; ++k) o[k] += sp.fref[4 * g + k];
+    for (int k = 0; k < 4; ++k) o[k] += fref[4 * g + k];
   }
+}
+
+// The OM reference of species s at grid row y: fref (16 FP64 values) and its
+// A-block moments sref (4 more).
+__device__ __forceinline__ const double *om_rowref(const InstDev &I, int s, int y) {
+  return I.rref + ((size_t)s * I.ny + y) * kRowRef;
+}
+// The same for the one-pass kernel, where s and y are wave-uniform: read
+// through the constant address space (scalar loads), re-read at each use.
+__device__ __forceinline__ const double DBM_CONST *om_rowref_c(const InstDev &I, int s, int y) {
+  return launder((const double DBM_CONST *)om_rowref(I, s, y));
 }
 
 // DPP broadcasts used by the halo transform: row_newbcast:n gives every lane
@@ -1832,7 +1848,7 @@ constexpr int kHoldRows = 3;
 //  * The update of row k is formed in the stored basis: the stencil
 //    increment projected onto it plus the moment-space collision, added to
 //    row k's stored values with one rounding.
-template <int S, int LIM, bool RKC, bool SR, bool CW>
+template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR>
 __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int x0, int y0,
                                               int rows, int in_idx, int fn_idx, int out_idx,
                                               float alpha, uint32_t step,
@@ -1873,7 +1889,8 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
   // as soon as they arrive (row r in slot r % 3 of the moment exchange).
   auto publish = [&](SpC &me, int r, const T *sv) {
     double n, jx, jy, E;
-    om_moments(me, sv, n, jx, jy, E);
+    if constexpr (RR) om_moments(me, om_rowref_c(I, s, r) + kNV, sv, n, jx, jy, E);
+    else om_moments(me, (const double DBM_CONST *)me.sref, sv, n, jx, jy, E);
     double(*mb)[kWave] = mom[r % 3];
     mb[0 * S + s][lane] = n;
     mb[1 * S + s][lane] = jx;
@@ -1919,6 +1936,20 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
   // its own row r) and parked in slot r % 3 of hhold until row r's update.
   auto halo_load = [&](int r) { return bin.lane_value(hplane, hcol + (uint32_t)(r * nx)); };
 
+  // fref(row r+1) - fref(row r), one value per velocity group (the planes of
+  // a group are equal at rest): the stencil's differences between rows are
+  // formed from the stored deviations and this.  Rows r and r+1 are read
+  // together (scalar loads) at the start of row r's update.
+  const float *dref = I.dref + (size_t)s * (ny + 4) * 4;
+  auto dref_rows = [&](int r, float *d0, float *d1) {
+    const float DBM_CONST *p = launder((const float DBM_CONST *)(dref + (size_t)(r + 2) * 4));
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      d0[g] = p[g];
+      d1[g] = p[4 + g];
+    }
+  };
+
   // Rows y0-2 .. y0+1: the stencil state of row y0 and the first two rows
   // of the hold.
   T c[kNV], y1[kNV], y2[kNV], nxv[kNV];
@@ -1944,16 +1975,23 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     om_recon(me, sb, rb);
     om_recon(me, s0, c);
     om_recon(me, s1, r1);
+    float da[4] = {0.f, 0.f, 0.f, 0.f}, db[4] = {0.f, 0.f, 0.f, 0.f}, d0[4] = {0.f, 0.f, 0.f, 0.f},
+          dn[4];
+    if constexpr (RR) {
+      dref_rows(y0 - 2, da, db);
+      dref_rows(y0, d0, dn);
+    }
 #pragma unroll
     for (int i = 0; i < kNV; ++i) {
       const int sy = plane_sy(i);
       if (sy > 0) {
-        y1[i] = c[i] - rb[i];
-        y2[i] = slope_pos<LIM>(rb[i] - ra[i], c[i] - rb[i]);
+        y1[i] = RR ? (c[i] - rb[i]) + db[i >> 2] : c[i] - rb[i];
+        y2[i] = slope_pos<LIM>(RR ? (rb[i] - ra[i]) + da[i >> 2] : rb[i] - ra[i], y1[i]);
         nxv[i] = r1[i];
       } else if (sy < 0) {
         y1[i] = r1[i];
-        y2[i] = slope_neg<LIM>(c[i] - rb[i], r1[i] - c[i]);
+        y2[i] = slope_neg<LIM>(RR ? (c[i] - rb[i]) + db[i >> 2] : c[i] - rb[i],
+                               RR ? (r1[i] - c[i]) + d0[i >> 2] : r1[i] - c[i]);
         nxv[i] = T(0);
       } else {
         y1[i] = y2[i] = T(0);
@@ -1984,8 +2022,24 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
                  bool &rfl) {
     if (k + kPf - 1 < yend) issue(k + kPf - 1, refill, hrefill, rfl);
     const int rk = k * nx;
+    // With references per row: this row's reference differences (rows k,
+    // k+1) and moments, scalar loads issued at the row's start and used by
+    // its stencils and collision.  With one reference for the grid the
+    // differences vanish and the moments are read where they are used.
+    float dk[4], dk1[4];
+    double sref_row[4];
+    if constexpr (RR) {
+      dref_rows(k, dk, dk1);
+      const double DBM_CONST *srp = om_rowref_c(I, s, k) + kNV;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sref_row[j] = srp[j];
+    }
     SpC *sp = launder(as_const(I.sp));
     SpC &me = sp[s];
+    auto sref_k = [&]() {
+      if constexpr (RR) return (const double *)sref_row;
+      else return (const double DBM_CONST *)me.sref;
+    };
     // Stored row k+2: hold it for its own update, reconstruct it for the
     // stencil (planes with v_y < 0 now, the others next row).
     T fnew[kNV];
@@ -2021,11 +2075,11 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     if constexpr (CW) {
       hold_get(k, sk);
       double n0, jx0, jy0, E0;
-      om_moments(me, sk, n0, jx0, jy0, E0);
+      om_moments(me, sref_k(), sk, n0, jx0, jy0, E0);
       __syncthreads();
       double(*cb)[kWave] = chn[k & 1];
       const double ux = cb[0][lane], uy = cb[1][lane], Tst = cb[2][lane], dn = cb[3 + s][lane];
-      collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
+      collision_rhs_om(I, me, sref_k(), sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
     }
     // x-halo of row k as f - fref, and its gathers to the edge lanes.
     T hf;
@@ -2084,7 +2138,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       }
       const T fn = nv[i];
       if (sy > 0) {
-        const T dn = fn - f;
+        const T dn = RR ? (fn - f) + dk[g] : fn - f;
         const T sk = slope_pos<LIM>(y1[i], dn);
         const T Dy = y1[i] + T(0.5) * (sk - y2[i]);
         a = fma(-cgy[g], Dy, a);
@@ -2093,7 +2147,8 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
         y2[i] = sk;
       } else if (sy < 0) {
         const T n1 = y1[i];
-        const T dlo = n1 - f, dhi = fn - n1;
+        const T dlo = RR ? (n1 - f) + dk[g] : n1 - f;
+        const T dhi = RR ? (fn - n1) + dk1[g] : fn - n1;
         const T tk1 = slope_neg<LIM>(dlo, dhi);
         const T Dy = dlo - T(0.5) * (tk1 - y2[i]);
         a = fma(cgy[g], Dy, a);
@@ -2119,7 +2174,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     if constexpr (!CW) {
       hold_get(k, sk);
       double n0, jx0, jy0, E0;
-      om_moments(me, sk, n0, jx0, jy0, E0);
+      om_moments(me, sref_k(), sk, n0, jx0, jy0, E0);
       double ux, uy, Tst, dn;
       double(*mb)[kWave] = mom[k & 1];
       mb[0 * S + s][lane] = n0;
@@ -2136,7 +2191,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
       ux = cs.ux;
       uy = cs.uy;
       Tst = cs.Tst;
-      collision_rhs_om(I, me, sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
+      collision_rhs_om(I, me, sref_k(), sk, n0, jx0, jy0, E0, n0 + dn, ux, uy, Tst, d);
     }
     T ds[kNV];
     om_project(me, dc, ds);
@@ -2187,7 +2242,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 
 // One workgroup = S wavefronts (plus the chain wavefront with CW), tiles
 // taken persistently in XCD-grouped order, as k_fused_stage.
-template <int S, int LIM, bool RKC, bool SR, bool CW>
+template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR>
 __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void k_fused_om(
     const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
     int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr) {
@@ -2203,7 +2258,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
     if (CW && s == S) {
       if constexpr (CW) chain_tile<float, S, 3>(insts[t.inst], t.y0, t.rows, mom, chn);
     } else {
-      fused_tile_om<S, LIM, RKC, SR, CW>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
+      fused_tile_om<S, LIM, RKC, SR, CW, RR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
                                           out_idx, alpha, step, mom, chn,
                                           hold[CW && s == S ? 0 : s], hhold[CW && s == S ? 0 : s]);
     }
@@ -2456,7 +2511,7 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
     }
     if (std::is_same<ST, float>::value && I.om) {
       float sv[kNV];
-      om_pack(sp, fe, sv);
+      om_pack(sp, om_rowref(I, s, (int)(cell / (size_t)I.nx)), fe, sv);
       for (int r = 0; r < kNV; ++r) ((float *)out.b)[(size_t)(s * kNV + r) * I.ps + cell] = sv[r];
     } else {
       for (int r = 0; r < kNV; ++r) out.set((size_t)(s * kNV + r) * I.ps + cell, fe[r]);
@@ -2473,7 +2528,7 @@ __device__ __forceinline__ void cell_f(const InstDev &I, const FV<ST> &f, int s,
     if (I.om) {
       float sv[kNV];
       for (int i = 0; i < kNV; ++i) sv[i] = ((const float *)f.b)[(size_t)(s * kNV + i) * I.ps + cell];
-      om_unpack(I.sp[s], sv, out);
+      om_unpack(I.sp[s], om_rowref(I, s, (int)(cell / (size_t)I.nx)), sv, out);
       return;
     }
   }
@@ -2762,7 +2817,7 @@ __global__ __launch_bounds__(256) void k_pack_om(const InstDev *__restrict__ ins
       const int p = s * kNV + i;
       fv[i] = p < half ? lo[(size_t)p * I.ps + cell] : hi[(size_t)(p - half) * I.ps + cell];
     }
-    om_pack(I.sp[s], fv, sv);
+    om_pack(I.sp[s], om_rowref(I, s, (int)(cell / (size_t)I.nx)), fv, sv);
     for (int i = 0; i < kNV; ++i) out[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
   }
 }
@@ -2777,11 +2832,12 @@ __global__ __launch_bounds__(256) void k_convert_om(const InstDev *__restrict__ 
     float sv[kNV];
     double fv[kNV];
     for (int i = 0; i < kNV; ++i) sv[i] = buf[(size_t)(s * kNV + i) * I.ps + cell];
+    const double *ref = om_rowref(I, s, (int)(cell / (size_t)I.nx));
     if (to_om) {
       for (int i = 0; i < kNV; ++i) fv[i] = sv[i];
-      om_pack(I.sp[s], fv, sv);
+      om_pack(I.sp[s], ref, fv, sv);
     } else {
-      om_unpack(I.sp[s], sv, fv);
+      om_unpack(I.sp[s], ref, sv, fv);
       for (int i = 0; i < kNV; ++i) sv[i] = (float)fv[i];
     }
     for (int i = 0; i < kNV; ++i) buf[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
@@ -2862,6 +2918,7 @@ struct FusedLaunch {
   double alpha, beta;
   bool split, pipe, sr, cw;  // split form, row pipeline, stochastic rounding, chain wavefront
   bool om;                   // FP32-bulk buffers in OM storage
+  bool rowref;               // ... with references per grid row (else one per grid)
   uint32_t *ctr;             // step counter of stochastic rounding
   hipStream_t st;
 };
@@ -2872,10 +2929,14 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
   if constexpr (std::is_same<ST, float>::value) {
     if (a.om) {
       if (a.pipe || a.split) return hipErrorInvalidValue;
-#define DBM_OM_LAUNCH(R, C)                                                                     \
-  hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C>), dim3(a.grid),                             \
+#define DBM_OM_LAUNCH2(R, C, Q)                                                                 \
+  hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C, Q>), dim3(a.grid),                          \
                      dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
                      a.in_idx, a.fn_idx, a.out_idx, (float)a.alpha, a.remap, a.ctr)
+#define DBM_OM_LAUNCH(R, C)                                                                     \
+  do {                                                                                          \
+    if (a.rowref) DBM_OM_LAUNCH2(R, C, true); else DBM_OM_LAUNCH2(R, C, false);                \
+  } while (0)
       if constexpr (S <= 3) {
         if (a.cw) {
           if (a.sr) DBM_OM_LAUNCH(true, true); else DBM_OM_LAUNCH(false, true);
@@ -2885,6 +2946,7 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
       if (a.cw) return hipErrorInvalidValue;
       if (a.sr) DBM_OM_LAUNCH(true, false); else DBM_OM_LAUNCH(false, false);
 #undef DBM_OM_LAUNCH
+#undef DBM_OM_LAUNCH2
       return hipGetLastError();
     }
   } else {
@@ -2950,7 +3012,7 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 // om: OM storage (FP32-bulk full form, no row pipeline); ctr: step counter
 // of stochastic rounding (two words of device memory).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, bool om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
+                        bool cw, int om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
                         int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
                         double beta, hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
@@ -2958,7 +3020,7 @@ hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pip
   if (cw && (split || pipe || S > 3)) return hipErrorInvalidValue;
   if (om && (prec != DBM_FP32_BULK || split || pipe)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
-                      alpha, beta, split, pipe, sr, cw, om, ctr, st};
+                      alpha, beta, split, pipe, sr, cw, om != 0, om == 2, ctr, st};
   switch (prec) {
     case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
     case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);
@@ -2983,7 +3045,7 @@ constexpr auto k_fused_stage_cw = k_fused_stage<ST, S, LIM, RKC, false, false, t
 // Workgroups of the stage kernel resident per CU (waves_per_cu), for the
 // full form, the split form (split) or the chain-wavefront form (cw).
 template <int S, int LIM, bool RKC, bool CW>
-constexpr auto k_fused_om_nr = k_fused_om<S, LIM, RKC, false, CW>;
+constexpr auto k_fused_om_nr = k_fused_om<S, LIM, RKC, false, CW, true>;
 
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
                            int *waves_per_cu) {

@@ -288,14 +288,14 @@ int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp,
     sp.wB2_f[k] = (float)(sp.omega * iB2[k]);
   }
   for (int k = 0; k < 16; ++k) sp.wE_f[k] = (float)(sp.omega * iE[k]);
-  // OM storage reference: none until the fields are set (fref = 0).
   return DBM_OK;
 }
 
-// Reference equilibrium of OM storage for one species: fref = f^eq(n_ref, 0,
-// T_ref) = M^{-1} fhat(n_ref, 0, 0, T_ref/m) (fhat at rest: the closed forms
-// listed after Eq.(14) with u = 0), and its A-block moments sref.
-void set_reference(SpeciesDev &sp, double n_ref, double T_ref) {
+// Reference equilibrium of OM storage for one species and grid row: fref =
+// f^eq(n_ref, 0, T_ref) = M^{-1} fhat(n_ref, 0, 0, T_ref/m) (fhat at rest: the
+// closed forms listed after Eq.(14) with u = 0), and its A-block moments
+// sref: out[0..15] = fref, out[16..19] = sref.
+void om_reference(const SpeciesDev &sp, double n_ref, double T_ref, double *out) {
   const double th = T_ref * sp.inv_m, K = sp.K;
   double h[kNV] = {0};
   h[0] = n_ref;
@@ -305,15 +305,16 @@ void set_reference(SpeciesDev &sp, double n_ref, double T_ref) {
   for (int r = 0; r < kNV; ++r) {
     double s = 0.0;
     for (int c = 0; c < kNV; ++c) s += sp.Minv[r * kNV + c] * h[c];
-    sp.fref[r] = s;
+    out[r] = s;
   }
-  for (int j = 0; j < 4; ++j) sp.sref[j] = 0.0;
+  double *sref = out + kNV;
+  for (int j = 0; j < 4; ++j) sref[j] = 0.0;
   for (int i = 0; i < kNV; ++i) {
-    const double f = sp.fref[i];
-    sp.sref[0] += sp.M[0 * kNV + i] * f;
-    sp.sref[1] += sp.M[3 * kNV + i] * f;
-    sp.sref[2] += (sp.M[4 * kNV + i] + sp.M[6 * kNV + i]) * f;
-    sp.sref[3] += (sp.M[13 * kNV + i] + sp.M[15 * kNV + i]) * f;
+    const double f = out[i];
+    sref[0] += sp.M[0 * kNV + i] * f;
+    sref[1] += sp.M[3 * kNV + i] * f;
+    sref[2] += (sp.M[4 * kNV + i] + sp.M[6 * kNV + i]) * f;
+    sref[3] += (sp.M[13 * kNV + i] + sp.M[15 * kNV + i]) * f;
   }
 }
 
