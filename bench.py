@@ -13,11 +13,13 @@ Prints ONE JSON line.  `value` is cell-species updates per second over the K
 timed steps (inputs resident in HBM; graph-replayed, one step per graph, the
 graphs captured during the W warm-up steps; the first ten or so launches of
 the stage kernel on C4 run up to 15% slower than the rest, so W defaults to
-20; C4 runs at 256 rows per tile, the autotuner's choice, pinned).  `roofline` is for the one-pass stage
-kernel: algorithmic bytes (32 values of f read and written per cell-species
-per Euler step) over its mean launch duration, which is the HIP-event time of
-the timed region (events recorded on the library's stream) divided by the
-launches in it.  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
+20; C4 runs at 256 rows per tile, the autotuner's choice, pinned).
+`roofline` is for the one-pass stage kernel: algorithmic bytes (32 values of
+f read and written per cell-species per Euler step) over its mean launch
+duration, which is the HIP-event time of the timed region (events recorded
+on the library's stream) divided by the launches in it; `traffic` is the
+measured HBM bytes per launch (FETCH_SIZE / WRITE_SIZE) while the kernel
+code is the one they were measured on.  `cpu_baseline` times the FP64 CPU oracle on a bounded sample
 of the same workload on this host.  `extra` holds the other configurations
 (C0-C3), other precisions and schemes, the plain FP64 GPU step, speedups at
 equal accuracy and the achievable-copy sweep.
@@ -51,18 +53,16 @@ UNIT = "cell-species updates/s"
 # and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
-    # of 9 eager launches at 256 rows per tile (Euler kernels; the source
-    # hash was moved forward over a change to the Runge-Kutta instantiations
-    # only, after checking that the Euler kernels' machine code is unchanged)
-    "c4/fp32/OM": {"source": "ff0c873cb0c9094b", "fetch_kib": 2248836.0625,
-                   "write_kib": 4194304.25,
-                   "bytes_per_launch": 2 * 2248836.0625 * 1024 + 4194304.25 * 1024},
-    "c4/fp32/f": {"source": "ff0c873cb0c9094b", "fetch_kib": 2577958.0625,
-                  "write_kib": 4194304.0,
-                  "bytes_per_launch": 2 * 2577958.0625 * 1024 + 4194304.0 * 1024},
-    "c4/fp64/f": {"source": "ff0c873cb0c9094b", "fetch_kib": 4980753.5625,
-                  "write_kib": 8388609.75,
-                  "bytes_per_launch": 2 * 4980753.5625 * 1024 + 8388609.75 * 1024},
+    # of the last 20 of the eager launches (C4: 256 rows per tile; C2: tuned)
+    "c4/fp32/OM": {"source": "878f028c387c8b2c", "fetch_kib": 2304057.9375,
+                   "write_kib": 4194304.3125,
+                   "bytes_per_launch": 1024 * (2 * 2304057.9375 + 4194304.3125)},
+    "c4/fp32/f": {"source": "878f028c387c8b2c", "fetch_kib": 2637867.65625, "write_kib": 4194304.0,
+                  "bytes_per_launch": 1024 * (2 * 2637867.65625 + 4194304.0)},
+    "c4/fp64/f": {"source": "878f028c387c8b2c", "fetch_kib": 4850160.3125, "write_kib": 8388611.875,
+                  "bytes_per_launch": 1024 * (2 * 4850160.3125 + 8388611.875)},
+    "c2/fp32/OM": {"source": "878f028c387c8b2c", "fetch_kib": 146498.46875, "write_kib": 262146.0,
+                   "bytes_per_launch": 1024 * (2 * 146498.46875 + 262146.0)},
 }
 
 
