@@ -246,16 +246,28 @@ enum {
                                path runs its full form without the row
                                pipeline: per cell and species the A-block
                                moments (n, E and two more) of f - fref and
-                               the orbit components B, X, Y of f, fref =
-                               f^eq(least n^s, 0, least T) over the cells,
-                               fixed when the fields or f are set; 1 the 16
-                               values f_i themselves.
-                               Both are 16 FP32 values per cell and species;
-                               OM storage rounds mass and energy relative to
-                               their deviation from fref and momentum
-                               relative to itself.  Setting it (or an option
-                               that excludes OM storage) converts the state
-                               in place; get: 0 OM storage in use, 1 f */
+                               the orbit components B, X, Y of f, fref an
+                               equilibrium at rest with the row means of
+                               n^s and T per grid row (the grid means for
+                               every row unless some row mean differs from
+                               them by more than 1e-3 of them), fixed when
+                               the fields or f are set; 1 the 16
+                               values f_i themselves; 2 OM storage where
+                               0 would use it, each A-block value also
+                               keeping the rounding remainder of its FP32
+                               value as a bfloat16 (8 more bytes per cell
+                               and species, summed in FP64 at each store:
+                               mass and energy to about 33 bits; round to
+                               nearest only, DBM_ERR_UNSUPPORTED with
+                               stochastic rounding).
+                               0 and 1 keep 16 FP32 values per cell and
+                               species; OM storage rounds mass and energy
+                               relative to their deviation from fref and
+                               momentum relative to itself.  Setting it (or
+                               an option that excludes OM storage) converts
+                               the state in place; get: 0 OM storage in
+                               use, 1 f, 2 OM storage with A-block
+                               residuals */
   DBM_OPT_CHAIN_WAVE = 11   /* one-pass path, nspecies <= 3: one more wavefront
                                per workgroup forms each row's mixture chain
                                (u, T, reaction) while the species' wavefronts

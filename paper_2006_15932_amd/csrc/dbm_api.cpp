@@ -19,11 +19,11 @@ namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
 void om_reference(const SpeciesDev &sp, double n_ref, double T_ref, double *out);
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, int om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
-                        int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
-                        double beta, hipStream_t st);
+                        bool cw, int om, bool ares, uint32_t *ctr, const InstDev *insts,
+                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
+                        int out_idx, double alpha, double beta, hipStream_t st);
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
-                           int *waves_per_cu);
+                           bool ares, int *waves_per_cu);
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
                         int in_idx, int fn_idx, int out_idx, double alpha, double beta, bool rkc,
                         bool sr, uint32_t *ctr, hipStream_t st);
@@ -31,7 +31,7 @@ hipError_t launch_widen_om(const InstDev *insts, int inst, size_t cells, int b, 
                            double *dst, hipStream_t st);
 hipError_t launch_pack_om(const InstDev *insts, int inst, size_t cells, const double *lo,
                           const double *hi, int b, hipStream_t st);
-hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, bool to_om,
+hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, int from, int to,
                              hipStream_t st);
 hipError_t launch_init(int prec, const InstDev *insts, int inst, size_t cells,
                        const double *fields, int out_idx, hipStream_t st);
@@ -170,7 +170,9 @@ int validate(const dbm_config *cfgs, int ninst) {
 }
 
 // Bytes per stored value (FP32X: 4-byte value + 2-byte residual) and per
-// value of the arithmetic type (plain-path scratch).
+// value of the arithmetic type (plain-path scratch).  An FP32-bulk buffer
+// also has room for the A-block residuals of OM storage (S x 4 uint16
+// planes after the S x 16 FP32 planes).
 size_t esize(const dbm_config &c) {
   return c.precision == DBM_FP32_BULK ? 4 : (c.precision == DBM_FP32X ? 6 : 8);
 }
@@ -178,6 +180,13 @@ size_t csize(const dbm_config &c) { return c.precision == DBM_FP32_BULK ? 4 : 8;
 // plane stride of the f buffers, in elements
 size_t pstride(const dbm_config &c) {
   return plane_stride((size_t)c.nx * c.ny, c.precision == DBM_FP64 ? 8 : 4);
+}
+// bytes of the values of one buffer, and of the A-block residuals (FP32-bulk)
+size_t fvalue_bytes(const dbm_config &c) {
+  return (size_t)c.nspecies * kNV * pstride(c) * esize(c);
+}
+size_t fares_bytes(const dbm_config &c) {
+  return c.precision == DBM_FP32_BULK ? (size_t)c.nspecies * 4 * pstride(c) * 2 : 0;
 }
 
 void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
@@ -221,7 +230,7 @@ void compute_layout(const dbm_config *cfgs, int ninst, Layout &L) {
   }
   for (int k = 0; k < ninst; ++k) {
     const size_t cells = (size_t)cfgs[k].nx * cfgs[k].ny;
-    const size_t fbytes = (size_t)S * kNV * pstride(cfgs[k]) * esize(cfgs[k]);
+    const size_t fbytes = fvalue_bytes(cfgs[k]) + fares_bytes(cfgs[k]);
     for (int b = 0; b < 3; ++b) {
       L.buf_off[b][k] = off;
       off = align_up(off + fbytes);
@@ -254,9 +263,11 @@ struct dbm_s {
   bool fp32 = false;     // FP32-bulk
   int prec = DBM_FP64;  // DBM_FP64 | DBM_FP32_BULK | DBM_FP32X
   int sr = 0;           // DBM_OPT_ROUNDING: 1 stochastic rounding of FP32 stores
-  int om_opt = 0;       // DBM_OPT_STORAGE: 0 OM storage where available, 1 f itself
+  int om_opt = 0;       // DBM_OPT_STORAGE: 0 OM storage where available, 1 f itself,
+                        // 2 OM storage with A-block residuals where available
   int device = 0;       // device current at dbm_create
   bool om = false;      // the buffers (every instance) hold OM storage
+  bool ares = false;    // ... with A-block residuals
   std::vector<SpeciesDev> tabs;  // host copy of the species tables
   // OM storage reference per instance and grid row: n_ref^s [s * ny + y] and
   // T_ref [y]; rowref[k]: instance k's references differ between rows (else
@@ -293,10 +304,17 @@ struct dbm_s {
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
   // workgroups resident on the device, per form
-  int resident = 0, resident_split = 0, resident_cw = 0, resident_om = 0, resident_om_cw = 0;
+  int resident = 0, resident_split = 0, resident_cw = 0, resident_om = 0, resident_om_cw = 0,
+      resident_ar = 0, resident_ar_cw = 0;
   int grid_cap() const {
+    if (om && ares) return cw ? resident_ar_cw : resident_ar;
     if (om) return cw ? resident_om_cw : resident_om;
     return split ? resident_split : (cw ? resident_cw : resident);
+  }
+  // resident workgroups of the chain-wavefront form of the storage in use
+  int cw_resident() const {
+    if (om && ares) return resident_ar_cw;
+    return om ? resident_om_cw : resident_cw;
   }
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   long long since_check = 0;
@@ -350,14 +368,14 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
       HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                          h->om_mode(), ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
+                          h->om_mode(), h->om && h->ares, ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
                           out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
         HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                            h->om_mode(), ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
+                            h->om_mode(), h->om && h->ares, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
                             fn_idx, out_idx, alpha, beta, st));
       }
     }
@@ -449,8 +467,8 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    (((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 3 +
-                        h->om_mode()};
+                    ((((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 3 +
+                     h->om_mode()) * 2 + (h->ares ? 1 : 0)};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -463,7 +481,7 @@ int ensure_tuned(dbm_handle h) {
     if (h->scheme == DBM_TVD_RK3) {  // give the timed stage realistic inputs
       for (int k = 0; k < h->ninst; ++k)
         HIPCHK(hipMemcpyAsync(h->inst[k].buf[1], h->inst[k].buf[0],
-                              (size_t)h->S * kNV * h->ps(k) * esize(h->cfg[k]),
+                              fvalue_bytes(h->cfg[k]) + fares_bytes(h->cfg[k]),
                               hipMemcpyDeviceToDevice, h->stream));
     }
     const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
@@ -475,7 +493,7 @@ int ensure_tuned(dbm_handle h) {
       // the row pipeline (pp 1) exists for the FP32 full form, the chain
       // wavefront (pp 2) for the full form with S <= 3
       const bool can_pipe = h->fp32 && f == 0 && !h->om;
-      const bool can_cw = f == 0 && h->S <= 3 && (h->om ? h->resident_om_cw : h->resident_cw) > 0;
+      const bool can_cw = f == 0 && h->S <= 3 && h->cw_resident() > 0;
       for (int pp = 0; pp < 3; ++pp) {
         if (pp == 1 && (!can_pipe || h->pipe_opt == 1)) continue;
         if (pp == 2 && (!can_cw || h->cw_opt == 1)) continue;
@@ -514,7 +532,7 @@ int ensure_tuned(dbm_handle h) {
     form = h->split_opt == 2 ? 1 : 0;
     if (form == 0 && h->fp32 && h->pipe_opt == 2) form = 2;
     if (form == 0 && h->cw_opt == 2 && h->S <= 3 &&
-        (h->om ? h->resident_om_cw : h->resident_cw) > 0)
+        h->cw_resident() > 0)
       form = 4;
   }
   if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) != 0) ||
@@ -603,12 +621,21 @@ int run_probe(dbm_handle h) {
 // its full form without the row pipeline, OM storage not switched off, and
 // the halo transform's lane broadcasts verified on this device.
 bool want_om(dbm_handle h) {
-  return h->prec == DBM_FP32_BULK && h->om_opt == 0 && use_fused(h) && h->split_opt != 2 &&
+  return h->prec == DBM_FP32_BULK && h->om_opt != 1 && use_fused(h) && h->split_opt != 2 &&
          h->pipe_opt != 2 && g_probe_om > 0 && h->resident_om > 0;
 }
+// ... and with A-block residuals (storage option 2; round to nearest).
+bool want_ares(dbm_handle h) {
+  return want_om(h) && h->om_opt == 2 && h->sr == 0 && h->resident_ar > 0;
+}
+// representation of the buffers: 0 f, 1 OM storage, 2 with A-block residuals
+int storage_mode(bool om, bool ares) { return om ? (ares ? 2 : 1) : 0; }
 
 int upload_inst(dbm_handle h) {
-  for (auto &d : h->inst) d.om = h->om ? 1 : 0;
+  for (auto &d : h->inst) {
+    d.om = h->om ? 1 : 0;
+    d.ares = h->om && h->ares ? 1 : 0;
+  }
   HIPCHK(hipMemcpyAsync(h->ws + h->L.inst_off, h->inst.data(), sizeof(InstDev) * h->ninst,
                         hipMemcpyHostToDevice, h->stream));
   return DBM_OK;
@@ -624,11 +651,13 @@ int upload_tables(dbm_handle h, int inst) {
 // Bring every instance's current buffer into the representation the options
 // ask for (FP32 f <-> OM storage, in place; FP64 arithmetic per cell).
 int sync_storage(dbm_handle h) {
-  const bool want = want_om(h);
-  if (want == h->om) return DBM_OK;
+  const bool want = want_om(h), want_ar = want_ares(h);
+  const int from = storage_mode(h->om, h->ares), to = storage_mode(want, want_ar);
+  if (from == to) return DBM_OK;
   for (int k = 0; k < h->ninst; ++k)
-    HIPCHK(launch_convert_om(h->d_inst(), k, h->cells(k), h->cur, want, h->stream));
+    HIPCHK(launch_convert_om(h->d_inst(), k, h->cells(k), h->cur, from, to, h->stream));
   h->om = want;
+  h->ares = want_ar;
   int rc = upload_inst(h);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -740,7 +769,8 @@ int set_om_reference(dbm_handle h, int inst, const std::vector<double> &n_row,
 
 // Checkpoint blob: this header, then the instance's current f buffer as
 // stored (S x 16 planes of stride ps in the storage precision, FP32X with its
-// residual planes), so that a restart continues bit for bit.
+// residual planes, OM storage with its A-block residuals when in use), so
+// that a restart continues bit for bit.
 struct StateHeader {
   uint64_t magic;
   int32_t prec, om, S, nx, ny, sr;
@@ -754,7 +784,7 @@ size_t state_ref_bytes(dbm_handle h, int inst) {
 }
 constexpr uint64_t kStateMagic = 0x4554415453424D44ULL;   // "DBMSTATE" in little-endian bytes
 size_t buffer_bytes(dbm_handle h, int inst) {
-  return (size_t)h->S * kNV * h->ps(inst) * esize(h->cfg[inst]);
+  return fvalue_bytes(h->cfg[inst]) + (h->om && h->ares ? fares_bytes(h->cfg[inst]) : 0);
 }
 
 int reset_counters(dbm_handle h) {
@@ -919,19 +949,20 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     return bail(fail(DBM_ERR_HIP, std::string("scratch symbol: ") + hipGetErrorString(e)));
   if (g_probe_state < 0) h->fused_ok = false;
   if (h->fused_ok) {
-    int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, per_cu_om = 0, per_cu_om_cw = 0, dev = 0;
+    int per_cu = 0, per_cu_split = 0, per_cu_cw = 0, per_cu_om = 0, per_cu_om_cw = 0,
+        per_cu_ar = 0, per_cu_ar_cw = 0, dev = 0;
     hipDeviceProp_t prop;
     const bool rk3 = h->scheme == DBM_TVD_RK3;
-    if ((e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, false, &per_cu)) !=
-            hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, true, false, false, &per_cu_split)) !=
-            hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, false, &per_cu_cw)) !=
-            hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, false, true, &per_cu_om)) !=
-            hipSuccess ||
-        (e = fused_occupancy(h->prec, h->S, h->lim, rk3, false, true, true, &per_cu_om_cw)) !=
-            hipSuccess ||
+    auto occ = [&](bool split, bool cw, bool om, bool ar, int *out) {
+      return fused_occupancy(h->prec, h->S, h->lim, rk3, split, cw, om, ar, out);
+    };
+    if ((e = occ(false, false, false, false, &per_cu)) != hipSuccess ||
+        (e = occ(true, false, false, false, &per_cu_split)) != hipSuccess ||
+        (e = occ(false, true, false, false, &per_cu_cw)) != hipSuccess ||
+        (e = occ(false, false, true, false, &per_cu_om)) != hipSuccess ||
+        (e = occ(false, true, true, false, &per_cu_om_cw)) != hipSuccess ||
+        (e = occ(false, false, true, true, &per_cu_ar)) != hipSuccess ||
+        (e = occ(false, true, true, true, &per_cu_ar_cw)) != hipSuccess ||
         (e = hipGetDevice(&dev)) != hipSuccess ||
         (e = hipGetDeviceProperties(&prop, dev)) != hipSuccess)
       return bail(fail(DBM_ERR_HIP, std::string("occupancy query: ") + hipGetErrorString(e)));
@@ -942,8 +973,12 @@ int dbm_create(const dbm_config *cfgs, int ninst, void *hip_stream, void *dev_wo
     h->resident_om = per_cu_om > 0 ? round_xcd(per_cu_om * prop.multiProcessorCount) : 0;
     h->resident_om_cw =
         per_cu_om_cw > 0 ? round_xcd(per_cu_om_cw * prop.multiProcessorCount) : 0;
+    h->resident_ar = per_cu_ar > 0 ? round_xcd(per_cu_ar * prop.multiProcessorCount) : 0;
+    h->resident_ar_cw =
+        per_cu_ar_cw > 0 ? round_xcd(per_cu_ar_cw * prop.multiProcessorCount) : 0;
   }
   h->om = want_om(h);
+  h->ares = want_ares(h);
   if ((rc = upload_inst(h)) || (rc = reset_counters(h))) return bail(rc);
   if ((e = hipStreamSynchronize(h->stream)) != hipSuccess)
     return bail(fail(DBM_ERR_HIP, std::string("set-up: ") + hipGetErrorString(e)));
@@ -1259,6 +1294,8 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       break;
     case DBM_OPT_ROUNDING:
       if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "rounding must be 0 or 1");
+      if (value == 1 && h->om_opt == 2)
+        return fail(DBM_ERR_UNSUPPORTED, "A-block residuals are summed with round to nearest");
       if (value == 1 && h->prec != DBM_FP32_BULK)
         return fail(DBM_ERR_UNSUPPORTED, "stochastic rounding applies to FP32-bulk storage");
       if (value == 1 && h->split_opt == 2)
@@ -1268,7 +1305,9 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       h->tiles.clear();
       break;
     case DBM_OPT_STORAGE:
-      if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "storage must be 0 or 1");
+      if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "storage must be 0, 1 or 2");
+      if (value == 2 && h->sr)
+        return fail(DBM_ERR_UNSUPPORTED, "A-block residuals are summed with round to nearest");
       h->om_opt = value;
       break;
     default: return fail(DBM_ERR_ARG, "unknown or read-only option");
@@ -1290,7 +1329,7 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_SPLIT: *value = h->split ? 2 : 1; break;
     case DBM_OPT_PIPELINE: *value = h->pipe ? 2 : 1; break;
     case DBM_OPT_ROUNDING: *value = h->sr; break;
-    case DBM_OPT_STORAGE: *value = h->om ? 0 : 1; break;
+    case DBM_OPT_STORAGE: *value = h->om ? (h->ares ? 2 : 0) : 1; break;
     case DBM_OPT_CHAIN_WAVE: *value = h->cw ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
@@ -1337,7 +1376,7 @@ int dbm_save_state(dbm_handle h, int inst, void *dst, size_t bytes) {
   std::memset(&hd, 0, sizeof(hd));
   hd.magic = kStateMagic;
   hd.prec = h->prec;
-  hd.om = h->om ? 1 : 0;
+  hd.om = storage_mode(h->om, h->ares);
   hd.S = h->S;
   hd.nx = h->cfg[inst].nx;
   hd.ny = h->cfg[inst].ny;
@@ -1361,8 +1400,8 @@ int dbm_load_state(dbm_handle h, int inst, const void *src, size_t bytes) {
   if (!src || bytes < sizeof(StateHeader)) return fail(DBM_ERR_ARG, "state buffer too small");
   StateHeader hd;
   std::memcpy(&hd, src, sizeof(hd));
-  if (hd.magic != kStateMagic || hd.prec != h->prec || hd.om != (h->om ? 1 : 0) || hd.S != h->S ||
-      hd.nx != h->cfg[inst].nx || hd.ny != h->cfg[inst].ny ||
+  if (hd.magic != kStateMagic || hd.prec != h->prec || hd.om != storage_mode(h->om, h->ares) ||
+      hd.S != h->S || hd.nx != h->cfg[inst].nx || hd.ny != h->cfg[inst].ny ||
       hd.buffer_bytes != buffer_bytes(h, inst) || bytes < dbm_state_bytes(h, inst))
     return fail(DBM_ERR_ARG, "state blob does not match this handle's configuration");
   const size_t ny = h->cfg[inst].ny, rb = state_ref_bytes(h, inst);

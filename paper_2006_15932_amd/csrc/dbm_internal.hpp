@@ -99,6 +99,9 @@ struct InstDev {
   double dt, dx, dy;
   int lim;
   int om;                // FP32-bulk buffers hold OM storage (see SpeciesDev)
+  int ares;              // ... with A-block residuals: four uint16 planes per
+                         // species (bfloat16 remainders of the A-block values)
+                         // after the S x 16 FP32 planes of every buffer
   // OM storage references, one per species and grid row (set with the
   // fields): rref[(s * ny + y) * kRowRef + 0..15] = fref of row y (FP64),
   // + 16..19 = its A-block moments sref; dref[(s * (ny + 4) + y + 2) * 4 +

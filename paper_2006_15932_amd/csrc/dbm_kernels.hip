@@ -380,6 +380,31 @@ template <typename ST> struct FBuf {
   }
 };
 
+// A-block residuals of OM storage (option of FP32-bulk): per species the
+// four A-block values also keep the rounding remainder of their FP32 value,
+// as a bfloat16 (the encoding of FP32X), in four uint16 planes of stride ps
+// that follow the S x 16 FP32 planes of the buffer.
+struct AResBuf {
+  rsrc_t r;
+  uint32_t plb;  // bytes per plane
+  __device__ AResBuf(const InstDev &I, int b, int s) {
+    plb = (uint32_t)I.ps * 2u;
+    r = make_rsrc((const uint16_t *)((const float *)I.buf[b] + nvals(I)) + (size_t)s * 4 * I.ps,
+                  4 * plb);
+  }
+  __device__ uint16_t value(uint32_t cell, uint32_t j) const {
+    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, (int)(cell * 2u), (int)(j * plb), 0);
+  }
+  __device__ void store(uint32_t cell, uint32_t j, uint16_t v) const {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, (int)(cell * 2u), (int)(j * plb), kStoreAux);
+  }
+};
+// The same residuals through plain pointers (conversion kernels), for the
+// buffer at `base`.
+__device__ __forceinline__ uint16_t *ares_ptr(const InstDev &I, const void *base, int s, int j) {
+  return (uint16_t *)((float *)base + nvals(I)) + (size_t)(s * 4 + j) * I.ps;
+}
+
 // Lane gather through the LDS crossbar: lane l gets v from lane addr[l] / 4.
 __device__ __forceinline__ float bperm(int addr, float v) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(addr, __float_as_int(v)));
@@ -1760,28 +1785,38 @@ __device__ __forceinline__ void collision_rhs_om(const InstDev &I, SpC &sp, P sr
 // FP64 conversions between f and OM storage (initialisation, transfers,
 // diagnostics and changes of representation).
 __device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *fref, const double *f,
-                                        float *s) {
+                                        double *s) {
   double A[4];
   for (int g = 0; g < 4; ++g) {
     const double c0 = f[4 * g] - fref[4 * g], c1 = f[4 * g + 1] - fref[4 * g + 1];
     const double c2 = f[4 * g + 2] - fref[4 * g + 2], c3 = f[4 * g + 3] - fref[4 * g + 3];
     A[g] = (c0 + c2) + (c1 + c3);
-    s[4 + g] = (float)((c0 + c2) - (c1 + c3));
+    s[4 + g] = (c0 + c2) - (c1 + c3);
     if ((g & 1) == 0) {
-      s[8 + g] = (float)(c0 - c2);
-      s[12 + g] = (float)(c1 - c3);
+      s[8 + g] = c0 - c2;
+      s[12 + g] = c1 - c3;
     } else {
-      s[8 + g] = (float)((c0 + c3) - (c1 + c2));
-      s[12 + g] = (float)((c0 + c1) - (c2 + c3));
+      s[8 + g] = (c0 + c3) - (c1 + c2);
+      s[12 + g] = (c0 + c1) - (c2 + c3);
     }
   }
   for (int j = 0; j < 4; ++j) {
     double m = 0.0;
     for (int g = 0; g < 4; ++g) m = fma(sp.MA[j * 4 + g], A[g], m);
-    s[j] = (float)m;
+    s[j] = m;
   }
 }
-__device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const double *fref, const float *s,
+// The stored FP32 values, and with `lo` the A-block residuals.
+__device__ __forceinline__ void om_pack(const SpeciesDev &sp, const double *fref, const double *f,
+                                        float *s, uint16_t *lo = nullptr) {
+  double d[kNV];
+  om_pack(sp, fref, f, d);
+  for (int i = 0; i < kNV; ++i) s[i] = (float)d[i];
+  if (lo)
+    for (int j = 0; j < 4; ++j) split_f32x(d[j], s[j], lo[j]);
+}
+template <typename V>
+__device__ __forceinline__ void om_unpack(const SpeciesDev &sp, const double *fref, const V *s,
                                           double *f) {
   for (int g = 0; g < 4; ++g) {
     double A = 0.0;
@@ -1848,7 +1883,11 @@ constexpr int kHoldRows = 3;
 //  * The update of row k is formed in the stored basis: the stencil
 //    increment projected onto it plus the moment-space collision, added to
 //    row k's stored values with one rounding.
-template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR>
+//  * With A-block residuals (AR) the four A-block values are summed in FP64
+//    with their residuals (loaded at the row's start) and stored as FP32
+//    plus a new residual: the stencils and the collision see the FP32
+//    values, the sum keeps what their rounding would drop each step.
+template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR, bool AR>
 __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int x0, int y0,
                                               int rows, int in_idx, int fn_idx, int out_idx,
                                               float alpha, uint32_t step,
@@ -1865,6 +1904,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
   const int lcol = map_x(col, nx, I.bcx);
   const bool writer = col < nx;
   const int yend = y0 + rows;
+  static_assert(!(AR && SR), "A-block residuals are summed with round to nearest");
 
   auto hold_put = [&](int r, const T *v) {
     float4_t(*h)[kWave] = hold[r % kHoldRows];
@@ -2026,6 +2066,13 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     // k+1) and moments, scalar loads issued at the row's start and used by
     // its stencils and collision.  With one reference for the grid the
     // differences vanish and the moments are read where they are used.
+    // A-block residuals of row k (and of f^n for the combine).
+    uint16_t rlo[4], rfn[4];
+    if constexpr (AR) {
+      const AResBuf ain(I, in_idx, s);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) rlo[j] = ain.value((uint32_t)(rk + lcol), j);
+    }
     float dk[4], dk1[4];
     double sref_row[4];
     if constexpr (RR) {
@@ -2215,8 +2262,23 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
         res[i] = sr_add(sk[i], dd, rb[i >> 2] >> (8 * (i & 3)));
       }
     } else {
+      if constexpr (AR && RKC) {
+        const AResBuf afn(I, fn_idx, s);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) rfn[j] = afn.value((uint32_t)(rkn + lcol), j);
+      }
 #pragma unroll
       for (int i = 0; i < kNV; ++i) {
+        if (AR && i < 4) {
+          double v = ((double)sk[i] + (double)bf16_value(rlo[i])) + (double)ds[i];
+          if constexpr (RKC) {
+            const T fn = kEarlyFn ? fnv[i] : bfn.value((uint32_t)(rkn + lcol), i);
+            const double fv = (double)fn + (double)bf16_value(rfn[i]);
+            v = fma((double)alpha, fv - v, v);
+          }
+          split_f32x(v, res[i], rlo[i]);
+          continue;
+        }
         res[i] = sk[i] + ds[i];
         if constexpr (RKC) {
           const T fn = kEarlyFn ? fnv[i] : bfn.value((uint32_t)(rkn + lcol), i);
@@ -2227,6 +2289,11 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     if (writer) {
 #pragma unroll
       for (int i = 0; i < kNV; ++i) bout.store((uint32_t)(rk + col), i, res[i]);
+      if constexpr (AR) {
+        const AResBuf aout(I, out_idx, s);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) aout.store((uint32_t)(rk + col), j, rlo[j]);
+      }
     }
   };
 
@@ -2242,7 +2309,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 
 // One workgroup = S wavefronts (plus the chain wavefront with CW), tiles
 // taken persistently in XCD-grouped order, as k_fused_stage.
-template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR>
+template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR, bool AR>
 __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void k_fused_om(
     const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
     int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr) {
@@ -2258,7 +2325,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
     if (CW && s == S) {
       if constexpr (CW) chain_tile<float, S, 3>(insts[t.inst], t.y0, t.rows, mom, chn);
     } else {
-      fused_tile_om<S, LIM, RKC, SR, CW, RR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
+      fused_tile_om<S, LIM, RKC, SR, CW, RR, AR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
                                           out_idx, alpha, step, mom, chn,
                                           hold[CW && s == S ? 0 : s], hhold[CW && s == S ? 0 : s]);
     }
@@ -2511,8 +2578,11 @@ __global__ __launch_bounds__(256) void k_init_eq(const InstDev *__restrict__ ins
     }
     if (std::is_same<ST, float>::value && I.om) {
       float sv[kNV];
-      om_pack(sp, om_rowref(I, s, (int)(cell / (size_t)I.nx)), fe, sv);
+      uint16_t lo[4];
+      om_pack(sp, om_rowref(I, s, (int)(cell / (size_t)I.nx)), fe, sv, I.ares ? lo : nullptr);
       for (int r = 0; r < kNV; ++r) ((float *)out.b)[(size_t)(s * kNV + r) * I.ps + cell] = sv[r];
+      if (I.ares)
+        for (int j = 0; j < 4; ++j) ares_ptr(I, out.b, s, j)[cell] = lo[j];
     } else {
       for (int r = 0; r < kNV; ++r) out.set((size_t)(s * kNV + r) * I.ps + cell, fe[r]);
     }
@@ -2526,8 +2596,10 @@ __device__ __forceinline__ void cell_f(const InstDev &I, const FV<ST> &f, int s,
                                        double *out) {
   if constexpr (std::is_same<ST, float>::value) {
     if (I.om) {
-      float sv[kNV];
+      double sv[kNV];
       for (int i = 0; i < kNV; ++i) sv[i] = ((const float *)f.b)[(size_t)(s * kNV + i) * I.ps + cell];
+      if (I.ares)
+        for (int j = 0; j < 4; ++j) sv[j] += (double)bf16_value(ares_ptr(I, f.b, s, j)[cell]);
       om_unpack(I.sp[s], om_rowref(I, s, (int)(cell / (size_t)I.nx)), sv, out);
       return;
     }
@@ -2817,30 +2889,44 @@ __global__ __launch_bounds__(256) void k_pack_om(const InstDev *__restrict__ ins
       const int p = s * kNV + i;
       fv[i] = p < half ? lo[(size_t)p * I.ps + cell] : hi[(size_t)(p - half) * I.ps + cell];
     }
-    om_pack(I.sp[s], om_rowref(I, s, (int)(cell / (size_t)I.nx)), fv, sv);
+    uint16_t rl[4];
+    om_pack(I.sp[s], om_rowref(I, s, (int)(cell / (size_t)I.nx)), fv, sv, I.ares ? rl : nullptr);
     for (int i = 0; i < kNV; ++i) out[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
+    if (I.ares)
+      for (int j = 0; j < 4; ++j) ares_ptr(I, out, s, j)[cell] = rl[j];
   }
 }
+// Changes the representation of buffer b in place, FP64 arithmetic per cell:
+// from / to 0 f itself, 1 OM storage, 2 OM storage with A-block residuals.
 __global__ __launch_bounds__(256) void k_convert_om(const InstDev *__restrict__ insts, int inst,
-                                                    int b, int to_om) {
+                                                    int b, int from, int to) {
   const InstDev &I = insts[inst];
   const size_t cells = (size_t)I.nx * I.ny;
   const size_t cell = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= cells) return;
   float *buf = (float *)I.buf[b];
   for (int s = 0; s < I.S; ++s) {
-    float sv[kNV];
     double fv[kNV];
-    for (int i = 0; i < kNV; ++i) sv[i] = buf[(size_t)(s * kNV + i) * I.ps + cell];
     const double *ref = om_rowref(I, s, (int)(cell / (size_t)I.nx));
-    if (to_om) {
-      for (int i = 0; i < kNV; ++i) fv[i] = sv[i];
-      om_pack(I.sp[s], ref, fv, sv);
+    if (from == 0) {
+      for (int i = 0; i < kNV; ++i) fv[i] = buf[(size_t)(s * kNV + i) * I.ps + cell];
     } else {
+      double sv[kNV];
+      for (int i = 0; i < kNV; ++i) sv[i] = buf[(size_t)(s * kNV + i) * I.ps + cell];
+      if (from == 2)
+        for (int j = 0; j < 4; ++j) sv[j] += (double)bf16_value(ares_ptr(I, buf, s, j)[cell]);
       om_unpack(I.sp[s], ref, sv, fv);
-      for (int i = 0; i < kNV; ++i) sv[i] = (float)fv[i];
     }
-    for (int i = 0; i < kNV; ++i) buf[(size_t)(s * kNV + i) * I.ps + cell] = sv[i];
+    float out[kNV];
+    uint16_t rl[4];
+    if (to == 0) {
+      for (int i = 0; i < kNV; ++i) out[i] = (float)fv[i];
+    } else {
+      om_pack(I.sp[s], ref, fv, out, to == 2 ? rl : nullptr);
+    }
+    for (int i = 0; i < kNV; ++i) buf[(size_t)(s * kNV + i) * I.ps + cell] = out[i];
+    if (to == 2)
+      for (int j = 0; j < 4; ++j) ares_ptr(I, buf, s, j)[cell] = rl[j];
   }
 }
 
@@ -2919,6 +3005,7 @@ struct FusedLaunch {
   bool split, pipe, sr, cw;  // split form, row pipeline, stochastic rounding, chain wavefront
   bool om;                   // FP32-bulk buffers in OM storage
   bool rowref;               // ... with references per grid row (else one per grid)
+  bool ares;                 // ... with A-block residuals
   uint32_t *ctr;             // step counter of stochastic rounding
   hipStream_t st;
 };
@@ -2929,24 +3016,35 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
   if constexpr (std::is_same<ST, float>::value) {
     if (a.om) {
       if (a.pipe || a.split) return hipErrorInvalidValue;
-#define DBM_OM_LAUNCH2(R, C, Q)                                                                 \
-  hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C, Q>), dim3(a.grid),                          \
+#define DBM_OM_LAUNCH3(R, C, Q, A)                                                              \
+  hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C, Q, A>), dim3(a.grid),                       \
                      dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
                      a.in_idx, a.fn_idx, a.out_idx, (float)a.alpha, a.remap, a.ctr)
 #define DBM_OM_LAUNCH(R, C)                                                                     \
   do {                                                                                          \
-    if (a.rowref) DBM_OM_LAUNCH2(R, C, true); else DBM_OM_LAUNCH2(R, C, false);                \
+    if (a.rowref) DBM_OM_LAUNCH3(R, C, true, false); else DBM_OM_LAUNCH3(R, C, false, false);  \
   } while (0)
+#define DBM_OM_LAUNCH_AR(C)                                                                     \
+  do {                                                                                          \
+    if (a.rowref) DBM_OM_LAUNCH3(false, C, true, true);                                         \
+    else DBM_OM_LAUNCH3(false, C, false, true);                                                 \
+  } while (0)
+      if (a.ares && a.sr) return hipErrorInvalidValue;
       if constexpr (S <= 3) {
         if (a.cw) {
-          if (a.sr) DBM_OM_LAUNCH(true, true); else DBM_OM_LAUNCH(false, true);
+          if (a.ares) DBM_OM_LAUNCH_AR(true);
+          else if (a.sr) DBM_OM_LAUNCH(true, true);
+          else DBM_OM_LAUNCH(false, true);
           return hipGetLastError();
         }
       }
       if (a.cw) return hipErrorInvalidValue;
-      if (a.sr) DBM_OM_LAUNCH(true, false); else DBM_OM_LAUNCH(false, false);
+      if (a.ares) DBM_OM_LAUNCH_AR(false);
+      else if (a.sr) DBM_OM_LAUNCH(true, false);
+      else DBM_OM_LAUNCH(false, false);
+#undef DBM_OM_LAUNCH_AR
 #undef DBM_OM_LAUNCH
-#undef DBM_OM_LAUNCH2
+#undef DBM_OM_LAUNCH3
       return hipGetLastError();
     }
   } else {
@@ -3009,18 +3107,20 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 // prec: DBM_FP64, DBM_FP32_BULK or DBM_FP32X (storage and arithmetic types).
 // sr: stochastic rounding of the stores (FP32-bulk full form only).
 // cw: chain wavefront (full form, S <= 3, no row pipeline).
-// om: OM storage (FP32-bulk full form, no row pipeline); ctr: step counter
-// of stochastic rounding (two words of device memory).
+// om: OM storage (FP32-bulk full form, no row pipeline): 1 one reference per
+// grid, 2 references per row; ares: with A-block residuals (round to nearest
+// only); ctr: step counter of stochastic rounding (two words of device memory).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, int om, uint32_t *ctr, const InstDev *insts, const Tile *tiles,
-                        int ntiles, int grid, int in_idx, int fn_idx, int out_idx, double alpha,
-                        double beta, hipStream_t st) {
+                        bool cw, int om, bool ares, uint32_t *ctr, const InstDev *insts,
+                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
+                        int out_idx, double alpha, double beta, hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   if (sr && (prec != DBM_FP32_BULK || split || !ctr)) return hipErrorInvalidValue;
   if (cw && (split || pipe || S > 3)) return hipErrorInvalidValue;
   if (om && (prec != DBM_FP32_BULK || split || pipe)) return hipErrorInvalidValue;
+  if (ares && (!om || sr)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
-                      alpha, beta, split, pipe, sr, cw, om != 0, om == 2, ctr, st};
+                      alpha, beta, split, pipe, sr, cw, om != 0, om == 2, ares, ctr, st};
   switch (prec) {
     case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
     case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);
@@ -3044,23 +3144,27 @@ constexpr auto k_fused_stage_cw = k_fused_stage<ST, S, LIM, RKC, false, false, t
                default: DBM_PICK1_CW(T, 3); break; }
 // Workgroups of the stage kernel resident per CU (waves_per_cu), for the
 // full form, the split form (split) or the chain-wavefront form (cw).
-template <int S, int LIM, bool RKC, bool CW>
-constexpr auto k_fused_om_nr = k_fused_om<S, LIM, RKC, false, CW, true>;
+template <int S, int LIM, bool RKC, bool CW, bool AR>
+constexpr auto k_fused_om_nr = k_fused_om<S, LIM, RKC, false, CW, true, AR>;
 
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
-                           int *waves_per_cu) {
+                           bool ares, int *waves_per_cu) {
   const void *fn = nullptr;
-  if (om) {   // OM storage: FP32-bulk full form
+  if (om) {   // OM storage: FP32-bulk full form (ares: with A-block residuals)
     if (prec != DBM_FP32_BULK || split || (cw && S > 3)) {
       *waves_per_cu = 0;
       return hipSuccess;
     }
-#define DBM_PICK_OM(SS, C)                                                                      \
+#define DBM_PICK_OM2(SS, C, A)                                                                  \
   fn = lim == DBM_LIM_MINMOD                                                                   \
-           ? (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, true, C>                   \
-                  : (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, false, C>)                 \
-           : (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, true, C>                     \
-                  : (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, false, C>)
+           ? (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, true, C, A>                \
+                  : (const void *)k_fused_om_nr<SS, DBM_LIM_MINMOD, false, C, A>)              \
+           : (rkc ? (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, true, C, A>                  \
+                  : (const void *)k_fused_om_nr<SS, DBM_LIM_NONE, false, C, A>)
+#define DBM_PICK_OM(SS, C)                                                                      \
+  do {                                                                                          \
+    if (ares) DBM_PICK_OM2(SS, C, true); else DBM_PICK_OM2(SS, C, false);                       \
+  } while (0)
     if (cw) {
       switch (S) { case 1: DBM_PICK_OM(1, true); break; case 2: DBM_PICK_OM(2, true); break;
                    default: DBM_PICK_OM(3, true); break; }
@@ -3070,6 +3174,7 @@ hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool 
                    default: return hipErrorInvalidValue; }
     }
 #undef DBM_PICK_OM
+#undef DBM_PICK_OM2
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(waves_per_cu, fn,
                                                         kWave * (S + (cw ? 1 : 0)), 0);
   }
@@ -3277,10 +3382,11 @@ hipError_t launch_pack_om(const InstDev *insts, int inst, size_t cells, const do
                      b);
   return hipGetLastError();
 }
-hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, bool to_om,
+hipError_t launch_convert_om(const InstDev *insts, int inst, size_t cells, int b, int from, int to,
                              hipStream_t st) {
+  if (from < 0 || from > 2 || to < 0 || to > 2) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_convert_om, dim3(blocks_for(cells, 256)), dim3(256), 0, st, insts, inst, b,
-                     (int)to_om);
+                     from, to);
   return hipGetLastError();
 }
 

@@ -3,14 +3,16 @@ workloads are stated with (velocity gated by max(max|u|, 0.01 c_s)).
 
 - The reacting premix at its full 256^2 size over its 5000 steps, FP32-bulk
   in OM storage (the default): rho, u, T within 1e-5.
-- The Rayleigh-Taylor setup's 128^2 crop over its 20000 steps: FP32X meets
-  1e-5 on rho, u, T; FP32-bulk in OM storage (references per grid row) with
-  stochastic rounding meets it on rho and T and on u against the sound
-  speed, while the flow stays below 1% of the sound speed, so u under the
-  floor (1.05e-5) is a known miss (test_gpu_known_misses.py).
+- The Rayleigh-Taylor setup's 128^2 crop over its 20000 steps: FP32-bulk in
+  OM storage with A-block residuals (storage 2) and FP32X meet 1e-5 on rho,
+  u, T; OM storage alone (references per grid row) meets it on rho and T,
+  and with stochastic rounding also on u against the sound speed, while the
+  flow stays below 1% of the sound speed, so u under the floor (5.1e-5,
+  1.05e-5) is a known miss (test_gpu_known_misses.py).
 - The batch's fast-reacting 128^2 instances over 2000 steps amplify any
-  storage rounding about 10^3: FP32X meets 1e-5; FP32-bulk in OM storage
-  meets it on instance 48, and on rho and T on instance 56 (u a known miss).
+  rounding about 10^3: FP32X meets 1e-5; FP32-bulk in OM storage, with or
+  without A-block residuals, meets it on instance 48, and on rho and T on
+  instance 56 (u a known miss).
 - FP64 storage within 1e-10 on rho and T at those step counts, and on u for
   the reacting premix; u of the Rayleigh-Taylor run: see
   test_rayleigh_taylor_20000_steps_fp64_velocity.
@@ -62,6 +64,9 @@ def test_rayleigh_taylor_crop_128_20000_steps():
     for k in ("rho", "T"):
         assert e[k] < TOL, ("fp32 OM storage", k, e)
     _errs(p, 20000, "fp32", mo, options={D.DBM_OPT_STORAGE: 1, D.DBM_OPT_ROUNDING: 1})
+    e = _errs(p, 20000, "fp32", mo, options={D.DBM_OPT_STORAGE: 2})
+    for k in ("rho", "u", "T"):
+        assert e[k] < TOL, ("fp32 OM storage with A-block residuals", k, e)
 
 
 @pytest.mark.parametrize("k", [48, 56])
@@ -77,6 +82,9 @@ def test_batch_instance_2000_steps(k):
         assert e[key] < TOL, ("fp32 OM", key, e)
     _errs(p, 2000, "fp32", mo, options={D.DBM_OPT_ROUNDING: 1})
     _errs(p, 2000, "fp32", mo, options={D.DBM_OPT_STORAGE: 1})
+    e = _errs(p, 2000, "fp32", mo, options={D.DBM_OPT_STORAGE: 2})
+    for key in (("rho", "u", "T") if k == 48 else ("rho", "T")):
+        assert e[key] < TOL, ("fp32 OM storage with A-block residuals", key, e)
 
 
 def test_rayleigh_taylor_20000_steps_fp64_within_1e10():

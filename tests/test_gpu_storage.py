@@ -3,10 +3,13 @@
 OM storage (DBM_OPT_STORAGE = 0, the default of FP32-bulk on the one-pass
 path) keeps per cell and species the A-block moments of f - fref (fref an
 equilibrium at rest per grid row, or one for the grid where the rows do not
-differ) and the orbit components B, X, Y of f in 16 FP32 values; the
-alternative stores the 16 values f_i.  Both are checked against the FP64 oracle, against each other,
-for independence of the tile shape and launch form, for conversions between
-them, and for bit-exact checkpoints through dbm_save_state / dbm_load_state.
+differ) and the orbit components B, X, Y of f in 16 FP32 values; storage 2
+adds a bfloat16 residual to each of the four A-block values (the sum is
+carried in FP64, the stencils and the collision see the FP32 values); the
+alternative stores the 16 values f_i.  All are checked against the FP64
+oracle, against each other, for independence of the tile shape and launch
+form, for conversions between them, and for bit-exact checkpoints through
+dbm_save_state / dbm_load_state.
 """
 import numpy as np
 import pytest
@@ -18,7 +21,7 @@ from paper_2006_15932_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 FP32_TOL = 1e-5
-OM, PLAIN = 0, 1
+OM, PLAIN, ARES = 0, 1, 2
 
 
 def test_storage_in_use_follows_the_options():
@@ -37,8 +40,22 @@ def test_storage_in_use_follows_the_options():
     for prec in ("fp64", "fp32x"):
         s2 = D.Simulation(p.with_(precision=prec), precision=prec)
         assert s2.get_option(D.DBM_OPT_STORAGE) == PLAIN
+    sim.set_option(D.DBM_OPT_STORAGE, ARES)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == ARES
+    with pytest.raises(D.DbmError) as e:
+        sim.set_option(D.DBM_OPT_ROUNDING, 1)
+    assert e.value.code == D.DBM_ERR_UNSUPPORTED
+    sim.set_option(D.DBM_OPT_PIPELINE, 2)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == PLAIN
+    sim.set_option(D.DBM_OPT_PIPELINE, 0)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == ARES
+    sim.set_option(D.DBM_OPT_STORAGE, OM)
+    sim.set_option(D.DBM_OPT_ROUNDING, 1)
+    with pytest.raises(D.DbmError) as e:
+        sim.set_option(D.DBM_OPT_STORAGE, ARES)
+    assert e.value.code == D.DBM_ERR_UNSUPPORTED
     with pytest.raises(D.DbmError):
-        sim.set_option(D.DBM_OPT_STORAGE, 2)
+        sim.set_option(D.DBM_OPT_STORAGE, 3)
 
 
 @pytest.mark.parametrize("case", ["reacting", "reacting_rk3", "shear4", "two_step", "outflow",
@@ -82,6 +99,72 @@ def test_om_storage_walls_and_force(n, ny, steps):
               {k: float("%.3e" % e[k]) for k in ("rho", "u", "u_cs", "T")}, flush=True)
         for k in ("rho", "u", "T"):
             assert e[k] < FP32_TOL, (k, e)
+
+
+@pytest.mark.parametrize("case", ["reacting", "reacting_rk3", "shear4", "walls_force", "chain3",
+                                  "ragged"])
+def test_om_residual_storage_matches_oracle(case):
+    """OM storage with A-block residuals (storage 2) against the FP64 oracle
+    (E1 metric, 1e-5): both schemes, four species, walls and gravity with
+    references per row, the chain wavefront, ragged sizes."""
+    p, steps, opts = {
+        "reacting": (W.reacting(n=70, ny=45, steps=1, precision="fp32"), 300, {}),
+        "reacting_rk3": (W.reacting(n=70, ny=45, steps=1, precision="fp32", scheme=W.RK3), 200,
+                         {}),
+        "shear4": (W.shear_layer(n=90, ny=64, steps=1, precision="fp32"), 40, {}),
+        "walls_force": (W.rayleigh_taylor(n=64, ny=48, steps=1, precision="fp32"), 300, {}),
+        "chain3": (W.reacting(n=70, ny=45, steps=1, precision="fp32"), 200,
+                   {D.DBM_OPT_CHAIN_WAVE: 2}),
+        "ragged": (W.reacting(n=65, ny=3, steps=1, precision="fp32"), 100, {}),
+    }[case]
+    print("case", case, p.nx, p.ny, "S=%d" % p.S, "steps", steps, flush=True)
+    o = dict(opts)
+    o[D.DBM_OPT_STORAGE] = ARES
+    sim = gpu_run(p, steps, "fp32", options=o)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == ARES
+    assert sim.get_option(D.DBM_OPT_PATH) == 0
+    if case == "chain3":
+        assert sim.get_option(D.DBM_OPT_CHAIN_WAVE) == 2
+    om, fo = oracle_run(p, steps)
+    e = field_errors(p, sim.moments(), om.moments(fo))
+    print("OM + residual errors", {k: float("%.3e" % v) for k, v in e.items()}, flush=True)
+    for k in ("rho", "u", "T"):
+        assert e[k] < FP32_TOL, (k, e)
+
+
+def test_om_residuals_reduce_the_density_and_energy_error():
+    """On the stratified column over 500 steps the A-block residuals cut the
+    density and temperature errors of OM storage (the rounding of mass and
+    energy at each store no longer accumulates)."""
+    p = W.rayleigh_taylor(n=64, ny=48, steps=1, precision="fp32")
+    o, fo = oracle_run(p, 500)
+    mo = o.moments(fo)
+    e = {}
+    for st in (OM, ARES):
+        sim = gpu_run(p, 500, "fp32", options={D.DBM_OPT_STORAGE: st})
+        assert sim.get_option(D.DBM_OPT_STORAGE) == st
+        e[st] = field_errors(p, sim.moments(), mo)
+        print("storage", st, {k: float("%.3e" % e[st][k]) for k in ("rho", "u", "T")}, flush=True)
+    assert e[ARES]["rho"] < 0.5 * e[OM]["rho"], e
+    assert e[ARES]["T"] < 0.5 * e[OM]["T"], e
+
+
+def test_om_residual_tile_shape_and_form_do_not_change_bits():
+    """Tile rows, the chain wavefront and graph replay leave every bit of the
+    state with A-block residuals unchanged."""
+    p = W.reacting(n=125, ny=41, steps=1, precision="fp32")
+    ref = None
+    for cw in (1, 2):
+        for rows in (1, 3, 16):
+            for graph in (1, 0):
+                o = {D.DBM_OPT_STORAGE: ARES, D.DBM_OPT_CHAIN_WAVE: cw, D.DBM_OPT_GRAPH: graph}
+                sim = gpu_run(p, 15, "fp32", tile_rows=rows, options=o)
+                assert sim.get_option(D.DBM_OPT_STORAGE) == ARES
+                f = sim.get_f()
+                if ref is None:
+                    ref = f
+                else:
+                    np.testing.assert_array_equal(f, ref, err_msg=str((cw, rows, graph)))
 
 
 def test_om_and_plain_storage_agree_to_fp32_rounding():
@@ -176,9 +259,37 @@ def test_conversion_between_representations():
         assert e[k] < FP32_TOL, (k, e)
 
 
+def test_conversion_to_and_from_residual_storage():
+    """OM storage -> with A-block residuals keeps the state to FP64 rounding
+    of the stored values; -> f storage and back rounds it to FP32 (B, X, Y
+    carry no residual); the residual storage then steps within 1e-5 of the
+    oracle (E1)."""
+    p = W.reacting(n=70, ny=45, steps=1, precision="fp32")
+    sim = gpu_run(p, 20, "fp32")
+    f_om = sim.get_f()
+    sim.set_option(D.DBM_OPT_STORAGE, ARES)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == ARES
+    assert f_error(sim.get_f(), f_om) < 1e-12
+    sim.set_option(D.DBM_OPT_STORAGE, PLAIN)
+    f_pl = sim.get_f()
+    assert f_error(f_pl, f_om) < 2e-7
+    sim.set_option(D.DBM_OPT_STORAGE, ARES)
+    assert f_error(sim.get_f(), f_pl) < 2e-7
+    sim.step(40)
+    o, fo = oracle_run(p, 60)
+    e = field_errors(p, sim.moments(), o.moments(fo))
+    for k in ("rho", "u", "T"):
+        assert e[k] < FP32_TOL, (k, e)
+    f_ar = sim.get_f()
+    sim.set_option(D.DBM_OPT_STORAGE, OM)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == OM
+    assert f_error(sim.get_f(), f_ar) < 2e-7
+
+
 def test_om_set_f_get_f_round_trip():
     """An arbitrary non-equilibrium f written with dbm_set_f and read back
-    agrees to FP32 rounding of the stored values."""
+    agrees to FP32 rounding of the stored values (and closer with A-block
+    residuals, which carry mass and energy to about 33 bits)."""
     p = W.reacting(n=67, ny=23, steps=1, precision="fp32")
     rng = np.random.default_rng(2006)
     f = 0.02 * (0.5 + rng.random((p.S, 16, p.ny, p.nx)))
@@ -188,11 +299,18 @@ def test_om_set_f_get_f_round_trip():
     sim.set_f(f)
     g = sim.get_f()
     assert f_error(g, f) < 1e-6
+    sim.set_option(D.DBM_OPT_STORAGE, ARES)
+    sim.set_f(f)
+    h = sim.get_f()
+    assert f_error(h, f) < 1e-6
+    mass = lambda x: x.sum(axis=(1, 2, 3))
+    assert np.abs(mass(h) - mass(f)).max() < 1e-9 * np.abs(mass(f)).max()
 
 
 @pytest.mark.parametrize("prec,opts", [("fp64", {}), ("fp32", {}), ("fp32x", {}),
                                        ("fp32", {D.DBM_OPT_STORAGE: PLAIN}),
-                                       ("fp32", {D.DBM_OPT_ROUNDING: 1})])
+                                       ("fp32", {D.DBM_OPT_ROUNDING: 1}),
+                                       ("fp32", {D.DBM_OPT_STORAGE: ARES})])
 def test_checkpoint_restart_is_bit_exact(prec, opts):
     """N steps equal N/2 steps, a saved state loaded into a new handle, and
     N/2 more steps, bit for bit (walls, force; every storage)."""
@@ -213,7 +331,8 @@ def test_load_state_rejects_a_blob_of_another_configuration():
     a = gpu_run(p, 2, "fp32")
     blob = a.save_state()
     for q, prec, opts in ((p.with_(nx=65), "fp32", {}), (p, "fp64", {}),
-                          (p, "fp32", {D.DBM_OPT_STORAGE: PLAIN})):
+                          (p, "fp32", {D.DBM_OPT_STORAGE: PLAIN}),
+                          (p, "fp32", {D.DBM_OPT_STORAGE: ARES})):
         b = D.Simulation(q, precision=prec)
         for k, v in opts.items():
             b.set_option(k, v)
