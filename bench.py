@@ -54,15 +54,21 @@ UNIT = "cell-species updates/s"
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
     # of the last 20 of the eager launches (C4: 256 rows per tile; C2: tuned)
-    "c4/fp32/OM": {"source": "878f028c387c8b2c", "fetch_kib": 2304057.9375,
-                   "write_kib": 4194304.3125,
-                   "bytes_per_launch": 1024 * (2 * 2304057.9375 + 4194304.3125)},
-    "c4/fp32/f": {"source": "878f028c387c8b2c", "fetch_kib": 2637867.65625, "write_kib": 4194304.0,
-                  "bytes_per_launch": 1024 * (2 * 2637867.65625 + 4194304.0)},
-    "c4/fp64/f": {"source": "878f028c387c8b2c", "fetch_kib": 4850160.3125, "write_kib": 8388611.875,
-                  "bytes_per_launch": 1024 * (2 * 4850160.3125 + 8388611.875)},
-    "c2/fp32/OM": {"source": "878f028c387c8b2c", "fetch_kib": 146498.46875, "write_kib": 262146.0,
-                   "bytes_per_launch": 1024 * (2 * 146498.46875 + 262146.0)},
+    "c4/fp32/OM": {"source": "a3a2311a995bf730", "fetch_kib": 2288447.71875,
+                   "write_kib": 4194304.1875,
+                   "bytes_per_launch": 1024 * (2 * 2288447.71875 + 4194304.1875)},
+    "c4/fp32/OM+AR": {"source": "a3a2311a995bf730", "fetch_kib": 2581655.03125,
+                      "write_kib": 4719104.5,
+                      "bytes_per_launch": 1024 * (2 * 2581655.03125 + 4719104.5)},
+    "c4/fp32/f": {"source": "a3a2311a995bf730", "fetch_kib": 2627235.8125, "write_kib": 4194304.0,
+                  "bytes_per_launch": 1024 * (2 * 2627235.8125 + 4194304.0)},
+    "c4/fp64/f": {"source": "a3a2311a995bf730", "fetch_kib": 4923444.375, "write_kib": 8388612.6875,
+                  "bytes_per_launch": 1024 * (2 * 4923444.375 + 8388612.6875)},
+    "c2/fp32/OM": {"source": "a3a2311a995bf730", "fetch_kib": 146483.8125, "write_kib": 262145.1875,
+                   "bytes_per_launch": 1024 * (2 * 146483.8125 + 262145.1875)},
+    "c2/fp32/OM+AR": {"source": "a3a2311a995bf730", "fetch_kib": 162893.875,
+                      "write_kib": 295424.1875,
+                      "bytes_per_launch": 1024 * (2 * 162893.875 + 295424.1875)},
 }
 
 
@@ -123,9 +129,19 @@ def workload(name: str, precision: str):
     raise SystemExit("unknown workload " + name)
 
 
-def bytes_per_csu(precision: str, scheme: int) -> int:
+def bytes_per_csu(precision: str, scheme: int, storage: str = "") -> int:
+    """Algorithmic bytes per cell-species update of one step: the 16 stored
+    values read and written once (Euler), 128 values moved over the three
+    stages of TVD-RK3; OM storage with A-block residuals also reads and
+    writes four 2-byte residuals per step (Euler)."""
     es = {"fp32": 4, "fp64": 8, "fp32x": 6}[precision]
+    if storage == "OM+AR":
+        assert scheme == 0, "A-block residual bytes are counted for Euler steps"
+        return es * 32 + 16
     return es * (32 if scheme == 0 else 128)
+
+
+STORAGE_NAMES = {0: "OM", 1: "f", 2: "OM+AR"}
 
 
 def gpu_run(p, precision, steps, warmup, tile_rows=0, rounding=0, chain_wave=0, storage=None,
@@ -162,7 +178,7 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0, rounding=0, chain_wave=0, 
     launches = steps * (1 if p.scheme == 0 else 3)
     info = {"tile_rows": sim.get_option(D.DBM_OPT_TILE_ROWS),
             "chain_wavefront": sim.get_option(D.DBM_OPT_CHAIN_WAVE) == 2,
-            "storage": "OM" if sim.get_option(D.DBM_OPT_STORAGE) == 0 else "f",
+            "storage": STORAGE_NAMES[sim.get_option(D.DBM_OPT_STORAGE)],
             "path": "one-pass" if sim.get_option(D.DBM_OPT_PATH) == 0 else "plain"}
     return sim, ms, ms / launches, info
 
@@ -184,6 +200,7 @@ def errors_vs_oracle(n=64, steps=200):
     mo = o.moments(fo)
     out = {}
     for key, prec, opts in (("fp32_om", "fp32", {}),
+                            ("fp32_om_residuals", "fp32", {D.DBM_OPT_STORAGE: 2}),
                             ("fp32_f_storage", "fp32", {D.DBM_OPT_STORAGE: 1}),
                             ("fp32_om_stochastic_rounding", "fp32", {D.DBM_OPT_ROUNDING: 1}),
                             ("fp32x", "fp32x", {}), ("fp64", "fp64", {})):
@@ -236,7 +253,8 @@ def small_config(name, precision, steps, **kw):
     kw.setdefault("chunk", steps)
     sim, ms, kern, info = gpu_run(p, precision, steps, steps, **kw)
     sim.close()
-    bpl = p.S * p.cells * bytes_per_csu(precision, p.scheme) / (1 if p.scheme == 0 else 3)
+    bpl = p.S * p.cells * bytes_per_csu(precision, p.scheme, info["storage"]) / (
+        1 if p.scheme == 0 else 3)
     return {"workload": desc, "precision": precision, "value": rate(p, steps, ms),
             "ms_per_step": ms / steps, "ms_per_launch": kern,
             "algorithmic_gbs": bpl / (kern * 1e-3) / 1e9,
@@ -350,8 +368,9 @@ def main():
                     help="chain wavefront (S <= 3): 0 autotune, 1 off, 2 on")
     ap.add_argument("--rounding", type=int, default=0, choices=[0, 1],
                     help="FP32 stores: 0 round to nearest, 1 stochastic")
-    ap.add_argument("--storage", type=int, default=-1, choices=[-1, 0, 1],
-                    help="FP32-bulk storage: -1 library default, 0 OM, 1 f itself")
+    ap.add_argument("--storage", type=int, default=-1, choices=[-1, 0, 1, 2],
+                    help="FP32-bulk storage: -1 library default, 0 OM, 1 f itself, 2 OM with "
+                         "A-block residuals")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
     args = ap.parse_args()
@@ -372,7 +391,7 @@ def main():
     sim.close()
     progress("timed run")
     value = rate(p, args.steps, ms)
-    bpl = p.S * p.cells * bytes_per_csu(args.precision, p.scheme)
+    bpl = p.S * p.cells * bytes_per_csu(args.precision, p.scheme, info["storage"])
     achieved = bpl / (kern_ms * 1e-3) / 1e9
     tr = MEASURED_TRAFFIC.get(args.workload + "/" + args.precision + "/" + info["storage"])
     traffic = None
@@ -405,14 +424,15 @@ def main():
         progress("copy sweep")
         # the same grid in other precisions and storages, and with TVD-RK3
         for key, prec, kw in (("fp32_f_storage", "fp32", {"storage": 1}),
+                              ("fp32_om_residuals", "fp32", {"storage": 2}),
                               ("fp32_om_stochastic_rounding", "fp32", {"rounding": 1}),
                               ("fp64", "fp64", {}), ("fp32x", "fp32x", {})):
             q, _ = workload(args.workload, prec)
             s2, ms2, k2, i2 = gpu_run(q, prec, 10, 2, **kw)
             s2.close()
             extra[key] = {"value": rate(q, 10, ms2), "ms_per_launch": k2,
-                          "frac": q.S * q.cells * bytes_per_csu(prec, 0) / (k2 * 1e-3) / 1e9
-                          / HBM_PEAK_GBS, **i2}
+                          "frac": q.S * q.cells * bytes_per_csu(prec, 0, i2["storage"])
+                          / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS, **i2}
             progress(key)
         q = p.with_(scheme=1)
         s3, ms3, k3, i3 = gpu_run(q, args.precision, 10, 2)
@@ -438,13 +458,18 @@ def main():
             extra["c1"]["value"] / extra["c1_plain_fp64"]["value"])
         extra["speedup_at_equal_accuracy"]["c1_fp64_one_pass_vs_plain_fp64"] = (
             extra["c1_fp64"]["value"] / extra["c1_plain_fp64"]["value"])
+        extra["c2"] = small_config("c2", "fp32", 500)
+        extra["c2_om_residuals"] = small_config("c2", "fp32", 500, storage=2)
+        extra["c2_stochastic_rounding"] = small_config("c2", "fp32", 500, rounding=1)
+        extra["c2_plain_fp64"] = small_config("c2", "fp64", 50, path=1)
+        extra["speedup_at_equal_accuracy"]["c2_fp32_om_residuals_vs_plain_fp64"] = (
+            extra["c2_om_residuals"]["value"] / extra["c2_plain_fp64"]["value"])
         extra["speedup_at_equal_accuracy"]["note"] = (
             "pairs only precisions that both meet their bar at the stated step count: FP64 "
-            "(one-pass and plain) always; FP32-bulk OM on C1 (256^2, 5000 steps within 1e-5, "
-            "tests/test_gpu_stated_steps.py); the shear layer has no full-size oracle at 5000 "
-            "steps, so FP32-bulk is not paired there")
-        extra["c2"] = small_config("c2", "fp32", 500)
-        extra["c2_stochastic_rounding"] = small_config("c2", "fp32", 500, rounding=1)
+            "(one-pass and plain) always; FP32-bulk OM on C1 (256^2, 5000 steps within 1e-5); "
+            "FP32-bulk OM with A-block residuals on C2 (its 128^2 crop, 20000 steps within "
+            "1e-5; tests/test_gpu_stated_steps.py); the shear layer has no full-size oracle "
+            "at 5000 steps, so FP32-bulk is not paired there")
         extra["c0_fp64"] = small_config("c0", "fp64", 1000)
         extra["c3"] = batched()
         progress("c2, c0, c3")

@@ -31,10 +31,19 @@ def test_kernel_hash_is_stable_and_stored_entries_are_well_formed():
     for key, entry in bench.MEASURED_TRAFFIC.items():
         wl, prec, storage = key.split("/")
         assert wl in ("c1", "c2", "c4") and prec in ("fp32", "fp64", "fp32x")
-        assert storage in ("OM", "f") and (storage == "f" or prec == "fp32")
+        assert storage in ("OM", "OM+AR", "f") and (storage == "f" or prec == "fp32")
         assert len(entry["source"]) == 16 and entry["bytes_per_launch"] > 0
         # FETCH_SIZE counts the kernels' 128 B reads as 64 B: scaled by 2
         assert entry["bytes_per_launch"] == 1024 * (2 * entry["fetch_kib"] + entry["write_kib"])
+
+
+def test_algorithmic_bytes_per_update():
+    # 16 values read and written once per Euler step; RK3 moves 128 values
+    assert bench.bytes_per_csu("fp32", 0) == 128 and bench.bytes_per_csu("fp64", 0) == 256
+    assert bench.bytes_per_csu("fp32x", 0) == 192 and bench.bytes_per_csu("fp32", 1) == 512
+    # A-block residuals: four 2-byte values more, each way
+    assert bench.bytes_per_csu("fp32", 0, "OM+AR") == 144
+    assert bench.STORAGE_NAMES == {0: "OM", 1: "f", 2: "OM+AR"}
 
 
 def test_default_tile_rows_apply_to_the_timed_workload_only():
