@@ -179,6 +179,7 @@ def gpu_run(p, precision, steps, warmup, tile_rows=0, rounding=0, chain_wave=0, 
     info = {"tile_rows": sim.get_option(D.DBM_OPT_TILE_ROWS),
             "chain_wavefront": sim.get_option(D.DBM_OPT_CHAIN_WAVE) == 2,
             "storage": STORAGE_NAMES[sim.get_option(D.DBM_OPT_STORAGE)],
+            "drain": sim.get_option(D.DBM_OPT_DRAIN) == 2,
             "path": "one-pass" if sim.get_option(D.DBM_OPT_PATH) == 0 else "plain"}
     return sim, ms, ms / launches, info
 

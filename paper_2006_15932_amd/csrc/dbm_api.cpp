@@ -19,9 +19,10 @@ namespace dbm {
 int build_species(const dbm_species &in, const dbm_config &cfg, SpeciesDev &sp, std::string &err);
 void om_reference(const SpeciesDev &sp, double n_ref, double T_ref, double *out);
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, int om, bool ares, uint32_t *ctr, const InstDev *insts,
-                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
-                        int out_idx, double alpha, double beta, hipStream_t st);
+                        bool cw, int om, bool ares, bool drain, uint32_t *ctr,
+                        const InstDev *insts, const Tile *tiles, int ntiles, int grid,
+                        int in_idx, int fn_idx, int out_idx, double alpha, double beta,
+                        hipStream_t st);
 hipError_t fused_occupancy(int prec, int S, int lim, bool rkc, bool split, bool cw, bool om,
                            bool ares, int *waves_per_cu);
 hipError_t launch_plain(int prec, const InstDev *insts, int inst, size_t cells, int S,
@@ -300,6 +301,9 @@ struct dbm_s {
   bool pipe = false;    // row pipelining in use (FP32 full form)
   int pipe_opt = 0;     // DBM_OPT_PIPELINE: 0 tuned, 1 off, 2 on
   bool cw = false;      // chain wavefront in use (full form, S <= 3)
+  bool drain = true;    // OM storage: every other row waits for its refill at once
+  int drain_opt = 0;    // DBM_OPT_DRAIN: 0 tuned with the tile rows (on when the
+                        // rows are set), 1 off, 2 on
   int cw_opt = 0;       // DBM_OPT_CHAIN_WAVE: 0 tuned, 1 off, 2 on
   std::vector<Tile> tiles;
   std::vector<int> tile_begin;
@@ -368,14 +372,14 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
       HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                          h->om_mode(), h->om && h->ares, ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
+                          h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
                           out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
         HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                            h->om_mode(), h->om && h->ares, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
+                            h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
                             fn_idx, out_idx, alpha, beta, st));
       }
     }
@@ -467,8 +471,8 @@ int ensure_tuned(dbm_handle h) {
   }
   const TuneKey key{h->prec, h->S, h->lim, h->scheme,
                     (int)std::lround(std::log2((double)tot + 1.0)), h->ninst,
-                    ((((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 3 +
-                     h->om_mode()) * 2 + (h->ares ? 1 : 0)};
+                    (((((h->split_opt * 3 + h->pipe_opt) * 3 + h->cw_opt) * 2 + h->sr) * 3 +
+                      h->om_mode()) * 2 + (h->ares ? 1 : 0)) * 3 + h->drain_opt};
   if (want <= 0) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -506,19 +510,27 @@ int ensure_tuned(dbm_handle h) {
           build_tiles(h, r);
           int rc = upload_tiles(h);
           if (rc) return rc;
-          double ms = 0.0;
-          if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
-          if ((rc = time_stage(h, 3, &ms))) return rc;
-          // short launches: about 1 ms of launches, compared by the median
-          const int reps = ms < 0.1 ? std::min(48, std::max(5, (int)(1.0 / std::max(ms, 1e-3)))) : 3;
-          if (reps > 3) {
-            double mean = 0.0;
-            if ((rc = time_stage(h, reps, &mean, &ms))) return rc;
-          }
-          if (ms < best) {
-            best = ms;
-            best_rows = r;
-            best_form = f | (pp == 1 ? 2 : 0) | (pp == 2 ? 4 : 0);
+          // OM storage: the refills kept in flight, or every other row's
+          // waited for at once (fewer loads in flight; the faster of the two
+          // depends on the workload)
+          for (int dr = 1; dr >= (h->om ? 0 : 1); --dr) {
+            if (h->om && h->drain_opt == 1 + dr) continue;   // the form not asked for
+            h->drain = dr == 1;
+            double ms = 0.0;
+            if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up
+            if ((rc = time_stage(h, 3, &ms))) return rc;
+            // short launches: about 1 ms of launches, compared by the median
+            const int reps =
+                ms < 0.1 ? std::min(48, std::max(5, (int)(1.0 / std::max(ms, 1e-3)))) : 3;
+            if (reps > 3) {
+              double mean = 0.0;
+              if ((rc = time_stage(h, reps, &mean, &ms))) return rc;
+            }
+            if (ms < best) {
+              best = ms;
+              best_rows = r;
+              best_form = f | (pp == 1 ? 2 : 0) | (pp == 2 ? 4 : 0) | (dr ? 8 : 0);
+            }
           }
         }
       }
@@ -534,12 +546,15 @@ int ensure_tuned(dbm_handle h) {
     if (form == 0 && h->cw_opt == 2 && h->S <= 3 &&
         h->cw_resident() > 0)
       form = 4;
+    if (h->drain_opt != 1) form |= 8;  // OM storage: every other row's refill waited for
   }
   if (want != h->rows || h->tiles.empty() || h->split != ((form & 1) != 0) ||
-      h->pipe != ((form & 2) != 0) || h->cw != ((form & 4) != 0)) {
+      h->pipe != ((form & 2) != 0) || h->cw != ((form & 4) != 0) ||
+      h->drain != ((form & 8) != 0)) {
     h->split = (form & 1) != 0;
     h->pipe = (form & 2) != 0;
     h->cw = (form & 4) != 0;
+    h->drain = (form & 8) != 0;
     build_tiles(h, want);
     int rc = upload_tiles(h);
     if (rc) return rc;
@@ -1292,6 +1307,12 @@ int dbm_set_option(dbm_handle h, int option, int value) {
       h->rows = 0;
       h->tiles.clear();
       break;
+    case DBM_OPT_DRAIN:
+      if (value < 0 || value > 2) return fail(DBM_ERR_ARG, "drain must be 0, 1 or 2");
+      h->drain_opt = value;
+      h->rows = 0;
+      h->tiles.clear();
+      break;
     case DBM_OPT_ROUNDING:
       if (value < 0 || value > 1) return fail(DBM_ERR_ARG, "rounding must be 0 or 1");
       if (value == 1 && h->om_opt == 2)
@@ -1331,6 +1352,7 @@ int dbm_get_option(dbm_handle h, int option, int *value) {
     case DBM_OPT_ROUNDING: *value = h->sr; break;
     case DBM_OPT_STORAGE: *value = h->om ? (h->ares ? 2 : 0) : 1; break;
     case DBM_OPT_CHAIN_WAVE: *value = h->cw ? 2 : 1; break;
+    case DBM_OPT_DRAIN: *value = h->drain ? 2 : 1; break;
     default: return fail(DBM_ERR_ARG, "unknown option");
   }
   return DBM_OK;

@@ -1887,10 +1887,14 @@ constexpr int kHoldRows = 3;
 //    with their residuals (loaded at the row's start) and stored as FP32
 //    plus a new residual: the stencils and the collision see the FP32
 //    values, the sum keeps what their rounding would drop each step.
+// s_waitcnt immediate (gfx9 encoding) that waits for every vector memory
+// operation of the wavefront (vmcnt 0) and for nothing else.
+constexpr int kWaitVmem0 = 0x0F70;
+
 template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR, bool AR>
 __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int x0, int y0,
                                               int rows, int in_idx, int fn_idx, int out_idx,
-                                              float alpha, uint32_t step,
+                                              float alpha, uint32_t step, int drain,
                                               double (*mom)[4 * S][kWave],
                                               double (*chn)[kChainRows<S, CW>][kWave],
                                               float4_t (*hold)[4][kWave], float (*hhold)[kWave]) {
@@ -2045,22 +2049,29 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     }
   }
 
-  // Ring slot of time t: stored row t+2 (with its reflection flag) and, for
-  // a row of the tile, its raw halo.
+  // Ring slot of time t: stored row t+2 (with its reflection flag) and its
+  // raw halo.  Every row issues its refill without a branch around it (past
+  // the tile's end the slot takes a row again, unused, and a halo row that
+  // is not updated is replaced by the tile's last, loaded and not parked):
+  // the compiler's count of loads in flight then stays exact, and the wait
+  // for the row that arrived leaves the loads issued after it in flight.
   auto issue = [&](int t, T *dst, T &halo, bool &flip) {
+    t = t < yend ? t : yend - 1;
     load_row(t + 2, dst, flip);
-    halo = t + 2 < yend ? halo_load(t + 2) : T(0);
+    halo = halo_load(t + 2 < yend ? t + 2 : yend - 1);
   };
   T ring[kPf][kNV];
   T hring[kPf];
   bool rflip[kPf];
 #pragma unroll
-  for (int d = 0; d < kPf - 1; ++d)
-    if (y0 + d < yend) issue(y0 + d, ring[d], hring[d], rflip[d]);
+  for (int d = 0; d < kPf - 1; ++d) issue(y0 + d, ring[d], hring[d], rflip[d]);
 
   auto row = [&](int k, const T *cur, const T hcur, const bool cflip, T *refill, T &hrefill,
                  bool &rfl) {
-    if (k + kPf - 1 < yend) issue(k + kPf - 1, refill, hrefill, rfl);
+    issue(k + kPf - 1, refill, hrefill, rfl);
+    // drain (a form the autotuner times against the other): every other row
+    // waits for its refill at once, which halves the loads in flight.
+    if (drain && ((k - y0) & 1) == 0) __builtin_amdgcn_s_waitcnt(kWaitVmem0);
     const int rk = k * nx;
     // With references per row: this row's reference differences (rows k,
     // k+1) and moments, scalar loads issued at the row's start and used by
@@ -2297,13 +2308,20 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
     }
   };
 
-  for (int k = y0; k < yend; k += kPf) {
+  // Whole rounds of the ring in the loop (no branch around a row), the
+  // rest after it.
+  int k = y0;
+  for (; k + kPf <= yend; k += kPf) {
 #pragma unroll
-    for (int d = 0; d < kPf; ++d) {
-      if (k + d < yend)
-        row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
-            hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
-    }
+    for (int d = 0; d < kPf; ++d)
+      row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+          hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+  }
+#pragma unroll
+  for (int d = 0; d < kPf - 1; ++d) {
+    if (k + d < yend)
+      row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+          hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
   }
 }
 
@@ -2312,7 +2330,7 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR, bool AR>
 __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void k_fused_om(
     const InstDev *__restrict__ insts, const Tile *__restrict__ tiles, int ntiles, int in_idx,
-    int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr) {
+    int fn_idx, int out_idx, float alpha, int remap, uint32_t *ctr, int drain) {
   __shared__ double mom[CW ? 3 : 2][4 * S][kWave];
   __shared__ double chn[CW ? 2 : 1][kChainRows<S, CW>][kWave];
   __shared__ float4_t hold[S][kHoldRows][4][kWave];
@@ -2326,7 +2344,7 @@ __global__ __launch_bounds__(kWave * (S + (CW ? 1 : 0)), DBM_MIN_WAVES_F32) void
       if constexpr (CW) chain_tile<float, S, 3>(insts[t.inst], t.y0, t.rows, mom, chn);
     } else {
       fused_tile_om<S, LIM, RKC, SR, CW, RR, AR>(insts[t.inst], s, t.x0, t.y0, t.rows, in_idx, fn_idx,
-                                          out_idx, alpha, step, mom, chn,
+                                          out_idx, alpha, step, drain, mom, chn,
                                           hold[CW && s == S ? 0 : s], hhold[CW && s == S ? 0 : s]);
     }
     __syncthreads();
@@ -3006,6 +3024,7 @@ struct FusedLaunch {
   bool om;                   // FP32-bulk buffers in OM storage
   bool rowref;               // ... with references per grid row (else one per grid)
   bool ares;                 // ... with A-block residuals
+  bool drain;                // ... every other row waits for its refill (k_fused_om)
   uint32_t *ctr;             // step counter of stochastic rounding
   hipStream_t st;
 };
@@ -3019,7 +3038,8 @@ static hipError_t launch_fused_t(const FusedLaunch &a) {
 #define DBM_OM_LAUNCH3(R, C, Q, A)                                                              \
   hipLaunchKernelGGL((k_fused_om<S, LIM, RKC, R, C, Q, A>), dim3(a.grid),                       \
                      dim3(kWave * (S + (C ? 1 : 0))), 0, a.st, a.insts, a.tiles, a.ntiles,      \
-                     a.in_idx, a.fn_idx, a.out_idx, (float)a.alpha, a.remap, a.ctr)
+                     a.in_idx, a.fn_idx, a.out_idx, (float)a.alpha, a.remap, a.ctr,          \
+                     (int)a.drain)
 #define DBM_OM_LAUNCH(R, C)                                                                     \
   do {                                                                                          \
     if (a.rowref) DBM_OM_LAUNCH3(R, C, true, false); else DBM_OM_LAUNCH3(R, C, false, false);  \
@@ -3109,18 +3129,21 @@ static hipError_t launch_fused_p(int S, int lim, bool rkc, const FusedLaunch &a)
 // cw: chain wavefront (full form, S <= 3, no row pipeline).
 // om: OM storage (FP32-bulk full form, no row pipeline): 1 one reference per
 // grid, 2 references per row; ares: with A-block residuals (round to nearest
-// only); ctr: step counter of stochastic rounding (two words of device memory).
+// only); drain: the OM kernel's form that waits for every other row's refill
+// at once; ctr: step counter of stochastic rounding (two words of device
+// memory).
 hipError_t launch_fused(int prec, int S, int lim, bool rkc, bool split, bool pipe, bool sr,
-                        bool cw, int om, bool ares, uint32_t *ctr, const InstDev *insts,
-                        const Tile *tiles, int ntiles, int grid, int in_idx, int fn_idx,
-                        int out_idx, double alpha, double beta, hipStream_t st) {
+                        bool cw, int om, bool ares, bool drain, uint32_t *ctr,
+                        const InstDev *insts, const Tile *tiles, int ntiles, int grid,
+                        int in_idx, int fn_idx, int out_idx, double alpha, double beta,
+                        hipStream_t st) {
   if (prec == DBM_FP32X && split) return hipErrorInvalidValue;  // full form only
   if (sr && (prec != DBM_FP32_BULK || split || !ctr)) return hipErrorInvalidValue;
   if (cw && (split || pipe || S > 3)) return hipErrorInvalidValue;
   if (om && (prec != DBM_FP32_BULK || split || pipe)) return hipErrorInvalidValue;
   if (ares && (!om || sr)) return hipErrorInvalidValue;
   const FusedLaunch a{insts, tiles, ntiles, grid, in_idx, fn_idx, out_idx, xcd_remap_flag(),
-                      alpha, beta, split, pipe, sr, cw, om != 0, om == 2, ares, ctr, st};
+                      alpha, beta, split, pipe, sr, cw, om != 0, om == 2, ares, drain, ctr, st};
   switch (prec) {
     case DBM_FP32_BULK: return launch_fused_p<float>(S, lim, rkc, a);
     case DBM_FP32X: return launch_fused_p<f32x>(S, lim, rkc, a);

@@ -30,6 +30,7 @@ DBM_OPT_PIPELINE = 9
 DBM_OPT_ROUNDING = 10
 DBM_OPT_CHAIN_WAVE = 11
 DBM_OPT_STORAGE = 12
+DBM_OPT_DRAIN = 13
 
 NV = 16
 

@@ -167,6 +167,26 @@ def test_om_residual_tile_shape_and_form_do_not_change_bits():
                     np.testing.assert_array_equal(f, ref, err_msg=str((cw, rows, graph)))
 
 
+@pytest.mark.parametrize("storage", [OM, ARES])
+def test_om_drain_forms_do_not_change_bits(storage):
+    """The OM kernel's two load forms (every other row waiting for its refill
+    at once, or the refills kept in flight) give identical bits at any tile
+    height, ragged last tiles included; the option reads back as set."""
+    p = W.shear_layer(n=125, ny=41, steps=1, precision="fp32")
+    ref = None
+    for drain in (2, 1):
+        for rows in (1, 2, 3, 7, 16):
+            sim = gpu_run(p, 12, "fp32", tile_rows=rows,
+                          options={D.DBM_OPT_STORAGE: storage, D.DBM_OPT_DRAIN: drain})
+            assert sim.get_option(D.DBM_OPT_STORAGE) == storage
+            assert sim.get_option(D.DBM_OPT_DRAIN) == drain
+            f = sim.get_f()
+            if ref is None:
+                ref = f
+            else:
+                np.testing.assert_array_equal(f, ref, err_msg=str((drain, rows)))
+
+
 def test_om_and_plain_storage_agree_to_fp32_rounding():
     p = W.reacting(n=70, ny=45, steps=1, precision="fp32")
     a = gpu_run(p, 50, "fp32")
