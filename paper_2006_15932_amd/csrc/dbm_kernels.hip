@@ -2055,10 +2055,17 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
   // is not updated is replaced by the tile's last, loaded and not parked):
   // the compiler's count of loads in flight then stays exact, and the wait
   // for the row that arrived leaves the loads issued after it in flight.
+  // (RK3 stages, which also hold f^n, keep the branches at the tile's end:
+  // without them the compiler's schedule does not fit their registers.)
   auto issue = [&](int t, T *dst, T &halo, bool &flip) {
-    t = t < yend ? t : yend - 1;
-    load_row(t + 2, dst, flip);
-    halo = halo_load(t + 2 < yend ? t + 2 : yend - 1);
+    if constexpr (RKC) {
+      load_row(t + 2, dst, flip);
+      halo = t + 2 < yend ? halo_load(t + 2) : T(0);
+    } else {
+      t = t < yend ? t : yend - 1;
+      load_row(t + 2, dst, flip);
+      halo = halo_load(t + 2 < yend ? t + 2 : yend - 1);
+    }
   };
   T ring[kPf][kNV];
   T hring[kPf];
@@ -2068,10 +2075,14 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 
   auto row = [&](int k, const T *cur, const T hcur, const bool cflip, T *refill, T &hrefill,
                  bool &rfl) {
-    issue(k + kPf - 1, refill, hrefill, rfl);
-    // drain (a form the autotuner times against the other): every other row
-    // waits for its refill at once, which halves the loads in flight.
-    if (drain && ((k - y0) & 1) == 0) __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+    if constexpr (RKC) {
+      if (k + kPf - 1 < yend) issue(k + kPf - 1, refill, hrefill, rfl);
+    } else {
+      issue(k + kPf - 1, refill, hrefill, rfl);
+      // drain (a form the autotuner times against the other): every other
+      // row waits for its refill at once, which halves the loads in flight.
+      if (drain && ((k - y0) & 1) == 0) __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+    }
     const int rk = k * nx;
     // With references per row: this row's reference differences (rows k,
     // k+1) and moments, scalar loads issued at the row's start and used by
@@ -2310,18 +2321,29 @@ __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int
 
   // Whole rounds of the ring in the loop (no branch around a row), the
   // rest after it.
-  int k = y0;
-  for (; k + kPf <= yend; k += kPf) {
+  if constexpr (RKC) {
+    for (int k = y0; k < yend; k += kPf) {
 #pragma unroll
-    for (int d = 0; d < kPf; ++d)
-      row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
-          hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
-  }
+      for (int d = 0; d < kPf; ++d) {
+        if (k + d < yend)
+          row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+              hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+      }
+    }
+  } else {
+    int k = y0;
+    for (; k + kPf <= yend; k += kPf) {
 #pragma unroll
-  for (int d = 0; d < kPf - 1; ++d) {
-    if (k + d < yend)
-      row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
-          hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+      for (int d = 0; d < kPf; ++d)
+        row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+            hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+    }
+#pragma unroll
+    for (int d = 0; d < kPf - 1; ++d) {
+      if (k + d < yend)
+        row(k + d, ring[d], hring[d], rflip[d], ring[(d + kPf - 1) % kPf],
+            hring[(d + kPf - 1) % kPf], rflip[(d + kPf - 1) % kPf]);
+    }
   }
 }
 
