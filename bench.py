@@ -54,21 +54,24 @@ UNIT = "cell-species updates/s"
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
     # of the last 20 of the eager launches (C4: 256 rows per tile; C2: tuned)
-    "c4/fp32/OM": {"source": "a3a2311a995bf730", "fetch_kib": 2288447.71875,
-                   "write_kib": 4194304.1875,
-                   "bytes_per_launch": 1024 * (2 * 2288447.71875 + 4194304.1875)},
-    "c4/fp32/OM+AR": {"source": "a3a2311a995bf730", "fetch_kib": 2581655.03125,
-                      "write_kib": 4719104.5,
-                      "bytes_per_launch": 1024 * (2 * 2581655.03125 + 4719104.5)},
-    "c4/fp32/f": {"source": "a3a2311a995bf730", "fetch_kib": 2627235.8125, "write_kib": 4194304.0,
-                  "bytes_per_launch": 1024 * (2 * 2627235.8125 + 4194304.0)},
-    "c4/fp64/f": {"source": "a3a2311a995bf730", "fetch_kib": 4923444.375, "write_kib": 8388612.6875,
-                  "bytes_per_launch": 1024 * (2 * 4923444.375 + 8388612.6875)},
-    "c2/fp32/OM": {"source": "a3a2311a995bf730", "fetch_kib": 146483.8125, "write_kib": 262145.1875,
-                   "bytes_per_launch": 1024 * (2 * 146483.8125 + 262145.1875)},
-    "c2/fp32/OM+AR": {"source": "a3a2311a995bf730", "fetch_kib": 162893.875,
-                      "write_kib": 295424.1875,
-                      "bytes_per_launch": 1024 * (2 * 162893.875 + 295424.1875)},
+    "c4/fp32/OM": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 2352031.40625, "write_kib": 4194304.0625,
+        "bytes_per_launch": 1024 * (2 * 2352031.40625 + 4194304.0625)},
+    "c4/fp32/OM+AR": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 2681891.75, "write_kib": 4718592.25,
+        "bytes_per_launch": 1024 * (2 * 2681891.75 + 4718592.25)},
+    "c4/fp32/f": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 2628900.75, "write_kib": 4194304.0,
+        "bytes_per_launch": 1024 * (2 * 2628900.75 + 4194304.0)},
+    "c4/fp64/f": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 4935496.28125, "write_kib": 8388613.4375,
+        "bytes_per_launch": 1024 * (2 * 4935496.28125 + 8388613.4375)},
+    "c2/fp32/OM": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 146493.09375, "write_kib": 262144.1875,
+        "bytes_per_launch": 1024 * (2 * 146493.09375 + 262144.1875)},
+    "c2/fp32/OM+AR": {"source": "a2d2decc886a98e8",
+        "fetch_kib": 174767.8125, "write_kib": 294912.0,
+        "bytes_per_launch": 1024 * (2 * 174767.8125 + 294912.0)},
 }
 
 
