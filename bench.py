@@ -53,7 +53,7 @@ UNIT = "cell-species updates/s"
 # and `traffic` is reported as null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
-    # of the last 20 of the eager launches (C4: 256 rows per tile; C2: tuned)
+    # of the last 20 of the eager launches (C4: 512 rows per tile; C2: tuned)
     "c4/fp32/OM": {"source": "a2d2decc886a98e8",
         "fetch_kib": 2352031.40625, "write_kib": 4194304.0625,
         "bytes_per_launch": 1024 * (2 * 2352031.40625 + 4194304.0625)},
@@ -76,10 +76,12 @@ MEASURED_TRAFFIC = {
 
 
 # Rows per tile of the timed run (0 = the library's autotuner).  On C4 the
-# autotuner picks 256 (128 and 512 are within 1%); pinning it keeps the
-# tuner's trial launches of the stage kernel out of the run, so that a
-# kernel trace of the run averages the timed configuration only.
-DEFAULT_TILE_ROWS = {"c4": 256}
+# autotuner's best are 256 and 512 rows, within 0.3% of each other; 512
+# gives each of the 512 resident workgroups one tile and reads 0.7% fewer
+# bytes (the 4-row y-halo of each tile).  Pinning it keeps the tuner's trial
+# launches of the stage kernel out of the run, so that a kernel trace of the
+# run averages the timed configuration only.
+DEFAULT_TILE_ROWS = {"c4": 512}
 
 
 def progress(what: str) -> None:

@@ -488,7 +488,7 @@ int ensure_tuned(dbm_handle h) {
                               fvalue_bytes(h->cfg[k]) + fares_bytes(h->cfg[k]),
                               hipMemcpyDeviceToDevice, h->stream));
     }
-    const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256};
+    const int cands[] = {1, 2, 4, 8, 16, 32, 64, 128, 256, 512};
     double best = 1e300;
     int best_rows = 1, best_form = form;
     for (int f = 0; f < 2; ++f) {

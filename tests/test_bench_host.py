@@ -47,4 +47,4 @@ def test_algorithmic_bytes_per_update():
 
 
 def test_default_tile_rows_apply_to_the_timed_workload_only():
-    assert bench.DEFAULT_TILE_ROWS == {"c4": 256}
+    assert bench.DEFAULT_TILE_ROWS == {"c4": 512}
