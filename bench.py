@@ -49,29 +49,31 @@ UNIT = "cell-species updates/s"
 # HBM bytes per launch of the one-pass stage kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs (profiles/fused_om_c4_counters.md), keyed by
 # workload, with the hash of the kernel code they were taken at (source
-# without comments, see code_text).  Changed kernel code makes the entry stale
-# and `traffic` is reported as null.
+# without comments, see code_text) and the rows per tile.  Changed kernel
+# code or other tile rows make the entry stale and `traffic` is reported as
+# null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2 (the copy calibration) + WRITE_SIZE, KiB x 1024, medians
-    # of the last 20 of the eager launches (C4: 512 rows per tile; C2: tuned)
-    "c4/fp32/OM": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 2352031.40625, "write_kib": 4194304.0625,
-        "bytes_per_launch": 1024 * (2 * 2352031.40625 + 4194304.0625)},
-    "c4/fp32/OM+AR": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 2681891.75, "write_kib": 4718592.25,
-        "bytes_per_launch": 1024 * (2 * 2681891.75 + 4718592.25)},
-    "c4/fp32/f": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 2628900.75, "write_kib": 4194304.0,
-        "bytes_per_launch": 1024 * (2 * 2628900.75 + 4194304.0)},
-    "c4/fp64/f": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 4935496.28125, "write_kib": 8388613.4375,
-        "bytes_per_launch": 1024 * (2 * 4935496.28125 + 8388613.4375)},
-    "c2/fp32/OM": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 146493.09375, "write_kib": 262144.1875,
-        "bytes_per_launch": 1024 * (2 * 146493.09375 + 262144.1875)},
-    "c2/fp32/OM+AR": {"source": "a2d2decc886a98e8",
-        "fetch_kib": 174767.8125, "write_kib": 294912.0,
-        "bytes_per_launch": 1024 * (2 * 174767.8125 + 294912.0)},
+    # of the last 20 of the eager launches at the rows per tile given
+    # (C4: the pinned rows; C2: the autotuner's)
+    "c4/fp32/OM": {"source": "a2d2decc886a98e8", "tile_rows": 512,
+        "fetch_kib": 2335371.0, "write_kib": 4194304.125,
+        "bytes_per_launch": 1024 * (2 * 2335371.0 + 4194304.125)},
+    "c4/fp32/OM+AR": {"source": "a2d2decc886a98e8", "tile_rows": 512,
+        "fetch_kib": 2669747.0, "write_kib": 4718592.0625,
+        "bytes_per_launch": 1024 * (2 * 2669747.0 + 4718592.0625)},
+    "c4/fp32/f": {"source": "a2d2decc886a98e8", "tile_rows": 512,
+        "fetch_kib": 2636329.53125, "write_kib": 4194304.0,
+        "bytes_per_launch": 1024 * (2 * 2636329.53125 + 4194304.0)},
+    "c4/fp64/f": {"source": "a2d2decc886a98e8", "tile_rows": 512,
+        "fetch_kib": 4895516.25, "write_kib": 8388612.5,
+        "bytes_per_launch": 1024 * (2 * 4895516.25 + 8388612.5)},
+    "c2/fp32/OM": {"source": "a2d2decc886a98e8", "tile_rows": 32,
+        "fetch_kib": 146490.9375, "write_kib": 262144.125,
+        "bytes_per_launch": 1024 * (2 * 146490.9375 + 262144.125)},
+    "c2/fp32/OM+AR": {"source": "a2d2decc886a98e8", "tile_rows": 16,
+        "fetch_kib": 174840.15625, "write_kib": 294912.0625,
+        "bytes_per_launch": 1024 * (2 * 174840.15625 + 294912.0625)},
 }
 
 
@@ -401,7 +403,7 @@ def main():
     achieved = bpl / (kern_ms * 1e-3) / 1e9
     tr = MEASURED_TRAFFIC.get(args.workload + "/" + args.precision + "/" + info["storage"])
     traffic = None
-    if tr and tr.get("source") == kernel_source_hash():
+    if tr and tr.get("source") == kernel_source_hash() and tr.get("tile_rows") == info["tile_rows"]:
         traffic = tr["bytes_per_launch"]
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,

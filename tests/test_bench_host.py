@@ -33,6 +33,7 @@ def test_kernel_hash_is_stable_and_stored_entries_are_well_formed():
         assert wl in ("c1", "c2", "c4") and prec in ("fp32", "fp64", "fp32x")
         assert storage in ("OM", "OM+AR", "f") and (storage == "f" or prec == "fp32")
         assert len(entry["source"]) == 16 and entry["bytes_per_launch"] > 0
+        assert entry["tile_rows"] >= 1
         # FETCH_SIZE counts the kernels' 128 B reads as 64 B: scaled by 2
         assert entry["bytes_per_launch"] == 1024 * (2 * entry["fetch_kib"] + entry["write_kib"])
 
