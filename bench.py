@@ -115,6 +115,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def stored_traffic(workload: str, precision: str, storage: str, tile_rows: int):
+    """HBM bytes per launch measured for this configuration, or None when
+    none was taken at the current kernel code and these rows per tile."""
+    tr = MEASURED_TRAFFIC.get(workload + "/" + precision + "/" + storage)
+    if tr and tr.get("source") == kernel_source_hash() and tr.get("tile_rows") == tile_rows:
+        return tr["bytes_per_launch"]
+    return None
+
+
 WORKLOADS = {
     "c0": "C0: 2-species Sod tube, 400x1, outflow x, FP64, Euler+NND, dt=1e-5, tau=2e-5",
     "c1": "C1: 3-species reacting premix, 256x256 periodic, Euler+NND, dt=1e-5, tau=2e-5",
@@ -401,10 +410,7 @@ def main():
     value = rate(p, args.steps, ms)
     bpl = p.S * p.cells * bytes_per_csu(args.precision, p.scheme, info["storage"])
     achieved = bpl / (kern_ms * 1e-3) / 1e9
-    tr = MEASURED_TRAFFIC.get(args.workload + "/" + args.precision + "/" + info["storage"])
-    traffic = None
-    if tr and tr.get("source") == kernel_source_hash() and tr.get("tile_rows") == info["tile_rows"]:
-        traffic = tr["bytes_per_launch"]
+    traffic = stored_traffic(args.workload, args.precision, info["storage"], info["tile_rows"])
     line = {
         "metric": METRIC, "value": value, "unit": UNIT, "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,

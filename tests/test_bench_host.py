@@ -47,5 +47,16 @@ def test_algorithmic_bytes_per_update():
     assert bench.STORAGE_NAMES == {0: "OM", 1: "f", 2: "OM+AR"}
 
 
+def test_stored_traffic_needs_the_same_code_and_tile_rows(monkeypatch):
+    entry = {"source": bench.kernel_source_hash(), "tile_rows": 512, "fetch_kib": 1.0,
+             "write_kib": 2.0, "bytes_per_launch": 4096.0}
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "c4/fp32/OM", entry)
+    assert bench.stored_traffic("c4", "fp32", "OM", 512) == 4096.0
+    assert bench.stored_traffic("c4", "fp32", "OM", 256) is None        # other tile rows
+    monkeypatch.setitem(bench.MEASURED_TRAFFIC, "c4/fp32/OM", dict(entry, source="0" * 16))
+    assert bench.stored_traffic("c4", "fp32", "OM", 512) is None        # other kernel code
+    assert bench.stored_traffic("c1", "fp32", "OM", 2) is None          # never measured
+
+
 def test_default_tile_rows_apply_to_the_timed_workload_only():
     assert bench.DEFAULT_TILE_ROWS == {"c4": 512}
