@@ -1869,6 +1869,10 @@ static_assert(kRingOM >= 2, "the prefetch ring needs two or more slots");
 typedef float float4_t __attribute__((ext_vector_type(4)));
 constexpr int kHoldRows = 3;
 
+// s_waitcnt immediate (gfx9 encoding) that waits for every vector memory
+// operation of the wavefront (vmcnt 0) and for nothing else.
+constexpr int kWaitVmem0 = 0x0F70;
+
 // One wavefront's share of a tile on OM storage (FP32-bulk): species `s`,
 // 64 lanes = columns x0 .. x0+63, rows y0 .. y0+rows-1, marching in +y.
 //  * Stored row r arrives two rows ahead (the look-ahead of planes with
@@ -1887,10 +1891,6 @@ constexpr int kHoldRows = 3;
 //    with their residuals (loaded at the row's start) and stored as FP32
 //    plus a new residual: the stencils and the collision see the FP32
 //    values, the sum keeps what their rounding would drop each step.
-// s_waitcnt immediate (gfx9 encoding) that waits for every vector memory
-// operation of the wavefront (vmcnt 0) and for nothing else.
-constexpr int kWaitVmem0 = 0x0F70;
-
 template <int S, int LIM, bool RKC, bool SR, bool CW, bool RR, bool AR>
 __device__ __forceinline__ void fused_tile_om(const InstDev &I, const int s, int x0, int y0,
                                               int rows, int in_idx, int fn_idx, int out_idx,
