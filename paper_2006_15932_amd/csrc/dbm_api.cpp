@@ -372,15 +372,16 @@ int enqueue_stage(dbm_handle h, int in_idx, int fn_idx, int out_idx, double alph
       const int nt = (int)h->tiles.size();
       const int grid = std::max(1, std::min(nt, h->grid_cap()));
       HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                          h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(), h->d_tiles(), nt, grid, in_idx, fn_idx,
-                          out_idx, alpha, beta, st));
+                          h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(),
+                          h->d_tiles(), nt, grid, in_idx, fn_idx, out_idx, alpha, beta, st));
     } else {
       for (int k = 0; k < h->ninst; ++k) {
         const int b = h->tile_begin[k], nt = h->tile_begin[k + 1] - b;
         const int grid = std::max(1, std::min(nt, h->grid_cap()));
         HIPCHK(launch_fused(h->prec, h->S, h->lim, rkc, h->split, h->pipe, h->sr != 0, h->cw,
-                            h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(), h->d_tiles() + b, nt, grid, in_idx,
-                            fn_idx, out_idx, alpha, beta, st));
+                            h->om_mode(), h->om && h->ares, h->om && h->drain, ctr, h->d_inst(),
+                            h->d_tiles() + b, nt, grid, in_idx, fn_idx, out_idx, alpha, beta,
+                            st));
       }
     }
   } else {
@@ -514,7 +515,7 @@ int ensure_tuned(dbm_handle h) {
           // waited for at once (fewer loads in flight; the faster of the two
           // depends on the workload)
           for (int dr = 1; dr >= (h->om ? 0 : 1); --dr) {
-            if (h->om && h->drain_opt == 1 + dr) continue;   // the form not asked for
+            if (h->om && h->drain_opt == 2 - dr) continue;   // the form not asked for
             h->drain = dr == 1;
             double ms = 0.0;
             if ((rc = time_stage(h, 1, &ms))) return rc;  // warm-up

@@ -185,6 +185,10 @@ def test_om_drain_forms_do_not_change_bits(storage):
                 ref = f
             else:
                 np.testing.assert_array_equal(f, ref, err_msg=str((drain, rows)))
+    for drain in (2, 1):   # asked for with tuned tile rows: the tuner keeps it
+        sim = gpu_run(p, 12, "fp32", options={D.DBM_OPT_STORAGE: storage, D.DBM_OPT_DRAIN: drain})
+        assert sim.get_option(D.DBM_OPT_DRAIN) == drain
+        np.testing.assert_array_equal(sim.get_f(), ref, err_msg="tuned rows, drain %d" % drain)
 
 
 def test_om_and_plain_storage_agree_to_fp32_rounding():
