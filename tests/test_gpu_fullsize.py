@@ -77,20 +77,24 @@ def test_reacting_256_fp64_sampled():
     _check(W.reacting(n=256, precision="fp64"), "fp64", 20, 1e-10)
 
 
-def test_batched_uneven_fp32_subset_within_1e5():
+@pytest.mark.parametrize("storage", [0, 2])
+def test_batched_uneven_fp32_subset_within_1e5(storage):
     """C3-style batch (uneven sizes, per-instance tau and hot-spot T) in one
-    persistent launch per stage, FP32-bulk, against the oracle per instance."""
+    persistent launch per stage, FP32-bulk (OM storage, and with A-block
+    residuals), against the oracle per instance."""
     import sys
     sys.path.insert(0, __file__.rsplit("/", 1)[0])
     from gpu_helpers import field_errors, oracle_run
     probs = W.batch(count=8, sizes=(32, 64, 96, 128), steps=200, precision="fp32")
     sim = D.Simulation(probs, precision="fp32")
+    sim.set_option(D.DBM_OPT_STORAGE, storage)
     for k in range(len(probs)):
         sim.set_fields(k)
     sim.step(200)
+    assert sim.get_option(D.DBM_OPT_STORAGE) == storage
     for k, p in enumerate(probs):
         o, fo = oracle_run(p, 200)
         e = field_errors(p, sim.moments(k), o.moments(fo))
-        print("batch instance", k, p.nx, e, flush=True)
+        print("batch instance", k, p.nx, "storage", storage, e, flush=True)
         for key in ("rho", "u", "T"):
             assert e[key] < 1e-5, (k, key, e)
