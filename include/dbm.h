@@ -268,13 +268,15 @@ enum {
                                the state in place; get: 0 OM storage in
                                use, 1 f, 2 OM storage with A-block
                                residuals */
-  DBM_OPT_DRAIN = 13,       /* one-pass kernel on OM storage: every other row
-                               waits for the loads of its refill (the row two
-                               ahead) at once, which halves the loads in
-                               flight; 0 tuned with the tile rows (default;
-                               on when the rows are set), 1 off (the refills
-                               stay in flight), 2 on; get: 1 or 2 in use.
-                               Results are the same bits either way */
+  DBM_OPT_DRAIN = 13,       /* one-pass kernel on OM storage, Euler stages
+                               (RK3 stages keep one form of their own):
+                               every other row waits for the loads of its
+                               refill (the row three ahead) at once, which
+                               halves the loads in flight; 0 tuned with the
+                               tile rows (default; on when the rows are
+                               set), 1 off (the refills stay in flight), 2
+                               on; get: 1 or 2 in use.  Results are the same
+                               bits either way */
   DBM_OPT_CHAIN_WAVE = 11   /* one-pass path, nspecies <= 3: one more wavefront
                                per workgroup forms each row's mixture chain
                                (u, T, reaction) while the species' wavefronts
