@@ -102,11 +102,12 @@ def test_om_storage_walls_and_force(n, ny, steps):
 
 
 @pytest.mark.parametrize("case", ["reacting", "reacting_rk3", "shear4", "walls_force", "chain3",
-                                  "ragged"])
+                                  "ragged", "two_step", "outflow"])
 def test_om_residual_storage_matches_oracle(case):
     """OM storage with A-block residuals (storage 2) against the FP64 oracle
     (E1 metric, 1e-5): both schemes, four species, walls and gravity with
-    references per row, the chain wavefront, ragged sizes."""
+    references per row, the chain wavefront, ragged sizes, two-step
+    chemistry, outflow boundaries."""
     p, steps, opts = {
         "reacting": (W.reacting(n=70, ny=45, steps=1, precision="fp32"), 300, {}),
         "reacting_rk3": (W.reacting(n=70, ny=45, steps=1, precision="fp32", scheme=W.RK3), 200,
@@ -116,6 +117,9 @@ def test_om_residual_storage_matches_oracle(case):
         "chain3": (W.reacting(n=70, ny=45, steps=1, precision="fp32"), 200,
                    {D.DBM_OPT_CHAIN_WAVE: 2}),
         "ragged": (W.reacting(n=65, ny=3, steps=1, precision="fp32"), 100, {}),
+        "two_step": (W.two_step(n=70, ny=33, precision="fp32"), 200, {}),
+        "outflow": (W.reacting(n=61, ny=33, steps=1, precision="fp32").with_(
+            bc_x=W.OUTFLOW, bc_y=W.OUTFLOW), 200, {}),
     }[case]
     print("case", case, p.nx, p.ny, "S=%d" % p.S, "steps", steps, flush=True)
     o = dict(opts)
@@ -167,12 +171,16 @@ def test_om_residual_tile_shape_and_form_do_not_change_bits():
                     np.testing.assert_array_equal(f, ref, err_msg=str((cw, rows, graph)))
 
 
-@pytest.mark.parametrize("storage", [OM, ARES])
-def test_om_drain_forms_do_not_change_bits(storage):
+@pytest.mark.parametrize("storage,case", [(OM, "shear4"), (ARES, "shear4"), (OM, "walls")])
+def test_om_drain_forms_do_not_change_bits(storage, case):
     """The OM kernel's two load forms (every other row waiting for its refill
     at once, or the refills kept in flight) give identical bits at any tile
-    height, ragged last tiles included; the option reads back as set."""
-    p = W.shear_layer(n=125, ny=41, steps=1, precision="fp32")
+    height, ragged last tiles included (also with walls and references per
+    row); the option reads back as set."""
+    if case == "shear4":
+        p = W.shear_layer(n=125, ny=41, steps=1, precision="fp32")
+    else:
+        p = W.rayleigh_taylor(n=125, ny=41, steps=1, precision="fp32")
     ref = None
     for drain in (2, 1):
         for rows in (1, 2, 3, 7, 16):
